@@ -1,0 +1,146 @@
+/*
+ * fdk.h - C ABI of the MI355X (gfx950) FDK cone-beam back-projection library.
+ *
+ * The method is the back-projection stage of FDK as restated by Chen et al.,
+ * "iFDK: A Scalable Framework for Instant High-resolution Image
+ * Reconstruction" (SC'19): every voxel is mapped through each view's
+ * projection geometry (Eq. 1, Eq. 2), the filtered projection is sampled
+ * bilinearly (Alg. 3) and the distance-weighted sample is accumulated into
+ * the volume (Alg. 2), using the reduced-cost coordinate scheme of Alg. 4
+ * (Theorems 1-3: u and z are constant along a z-column, v is linear in k,
+ * mirrored slices share v).
+ *
+ * Conventions shared by every entry point
+ *  - Lengths share one unit (Table 1 mixes "pixel" and "mm"; Eq. 3 adds d to
+ *    D_x * index, so they must agree).
+ *  - Volume arrays are (Nz_local, Ny, Nx) FP32, x fastest: element (i,j,k) of
+ *    the slab is vol[((k_local * Ny) + j) * Nx + i].
+ *  - Projection arrays are (nviews, Nv, Nu), u fastest: q[(s*Nv + v)*Nu + u]
+ *    holds view view0+s.
+ *  - Device pointers are HIP device (or managed) memory owned by the caller,
+ *    who keeps them alive until the work on `stream` completes. Host
+ *    pointers (the geometry and its angle array) are read during the call
+ *    only and may be freed on return.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Every call is asynchronous on that stream and allocates no device
+ *    memory.
+ *  - Errors: arguments are validated on the host before anything is
+ *    enqueued. A failed call returns a non-zero fdk_status, enqueues nothing
+ *    (except FDK_ERR_HIP, reported after a launch failed) and leaves a
+ *    message for fdk_last_error() in the calling thread. No call aborts or
+ *    throws across the ABI.
+ */
+#ifndef FDK_H_
+#define FDK_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FDK_OK = 0,
+  FDK_ERR_INVALID_ARG = 1, /* a pointer, size, range or geometry is invalid */
+  FDK_ERR_UNSUPPORTED = 2, /* a dtype, filter or slab kind this build lacks */
+  FDK_ERR_HIP = 3,         /* the HIP runtime reported an error */
+  FDK_ERR_OUT_OF_MEMORY = 4
+} fdk_status;
+
+/* Storage type of filtered projections. Arithmetic is FP32 throughout. */
+typedef enum { FDK_F32 = 0, FDK_F16 = 1, FDK_BF16 = 2 } fdk_dtype;
+
+/* Ramp kernels of the filtering stage (Alg. 1; the paper defers F_ramp to
+ * the FDK literature): Ram-Lak and Shepp-Logan, sampled at the detector
+ * pitch scaled to the rotation axis. */
+typedef enum { FDK_RAMLAK = 0, FDK_SHEPP_LOGAN = 1 } fdk_filter_kind;
+
+/* Which global slices a volume buffer holds.
+ * FDK_SLAB_CONTIGUOUS : slices [z0, z0 + nz_local) in order.
+ * FDK_SLAB_MIRROR_PAIR: a mirrored pair of slabs as in the paper's 2R
+ *   sub-volumes (Fig. 5): with h = nz_local / 2, slices [z0, z0 + h)
+ *   followed by [Nz - z0 - h, Nz - z0), each in ascending global k. */
+typedef enum { FDK_SLAB_CONTIGUOUS = 0, FDK_SLAB_MIRROR_PAIR = 1 } fdk_slab_kind;
+
+/* flags: accumulate into the output instead of overwriting it. */
+#define FDK_ACCUMULATE 1u
+
+/* Circular-orbit cone-beam geometry (Table 1; projection matrix Eq. 2).
+ * The volume centre (voxel ((Nx-1)/2, (Ny-1)/2, (Nz-1)/2)) is on the
+ * rotation axis; the principal point is pixel ((Nu-1)/2 + off_u,
+ * (Nv-1)/2 + off_v); view s is taken at gantry angle angles[s]. */
+typedef struct {
+  int32_t nx, ny, nz;    /* full volume, voxels */
+  double dx, dy, dz;     /* voxel pitch */
+  int32_t nu, nv;        /* detector, pixels */
+  double du, dv;         /* pixel pitch */
+  double off_u, off_v;   /* principal-point shift, pixels (0 in the paper) */
+  double sod;            /* d: source to rotation axis */
+  double sdd;            /* D: source to detector */
+  int32_t np;            /* number of views in the scan */
+  const double* angles;  /* HOST array of np gantry angles beta, radians */
+} fdk_geometry;
+
+/* Filtering stage, Alg. 1: for views [view0, view0 + nviews), multiply each
+ * line-integral image by the cosine weight D / sqrt(D^2 + a^2 + b^2) (a, b:
+ * the pixel's offset from the principal point on the detector) and convolve
+ * every detector row (linear convolution, zero outside the row) with the
+ * ramp kernel h sampled at tau = Du * d / D:
+ *     Q(u) = tau * sum_n h(u - n) * E~(n).
+ * e: device FP32 (nviews, Nv, Nu). q: device (nviews, Nv, Nu) of out_dtype,
+ * must not overlap e. The FDK constant pi * d^2 / Np is NOT applied here (it
+ * is fdk_backproject's `scale`), which keeps 16-bit storage in range.
+ * Errors: FDK_ERR_INVALID_ARG for a bad geometry, range or null pointer;
+ * FDK_ERR_UNSUPPORTED for an unknown kind or dtype, or Nu above 8192. */
+fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                      const float* e, void* q, fdk_dtype out_dtype,
+                      fdk_filter_kind kind, void* stream);
+
+/* Back-projection, Alg. 2 computed as Alg. 4. For every voxel (i, j, k)
+ * the slab holds, with [x, y, z] = P_s [i, j, k, 1], f = 1/z, W = f^2,
+ * (u, v) = (x f, y f):
+ *     vol(i,j,k) (+)= scale * sum_{s in [view0, view0+nviews)} W * interp2(Q_s, u, v)
+ * interp2 is Alg. 3 with floor for int() and taps outside the detector
+ * reading zero. q: device (nviews, Nv, Nu) of q_dtype (FP32, FP16 or BF16;
+ * accumulation is FP32). vol: device FP32 slab, see fdk_slab_kind; z0 and
+ * nz_local select its global slices. Without FDK_ACCUMULATE the slab is
+ * overwritten (nviews = 0 then zeroes it). For FDK pass
+ * scale = fdk_fdk_scale(g). Each voxel is owned by one thread that sums the
+ * views in a fixed order: results are bitwise reproducible run to run.
+ * Errors: FDK_ERR_INVALID_ARG for a null pointer, non-positive size, view
+ * range outside [0, np), slab outside the volume (or an odd nz_local /
+ * overlapping halves for a mirror pair), sod not larger than the volume's
+ * half-diagonal in x-y (some z <= 0, Eq. 3), sdd <= 0, or a non-finite value. */
+fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                           const void* q, fdk_dtype q_dtype, float* vol,
+                           int32_t z0, int32_t nz_local, fdk_slab_kind slab,
+                           float scale, uint32_t flags, void* stream);
+
+/* Forward projection: the exact adjoint (transpose) of fdk_backproject with
+ * the same geometry, views, slab and scale, i.e. for all q and x
+ *     <fdk_backproject(q), x> = <q, fdk_forward_project(x)>.
+ * Every voxel of the slab adds scale * W * w_tap * vol(i,j,k) to each of its
+ * four bilinear taps that lies inside the detector, with the identical
+ * coordinates and weights the back-projector uses. vol: device FP32 slab.
+ * q: device FP32 (nviews, Nv, Nu), overwritten unless FDK_ACCUMULATE. Uses
+ * floating-point atomics, so the last bits vary from run to run.
+ * Errors: as fdk_backproject. */
+fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                               const float* vol, int32_t z0, int32_t nz_local,
+                               fdk_slab_kind slab, float* q, float scale,
+                               uint32_t flags, void* stream);
+
+/* pi * d^2 / Np: the FDK constant (1/2) * (2 pi / Np) * d^2 of a full
+ * 360-degree scan, since W = 1/z^2 carries no d^2. Returns NaN for a null
+ * or invalid geometry. */
+double fdk_fdk_scale(const fdk_geometry* g);
+
+/* Message describing the calling thread's most recent failed call ("" if
+ * none). Valid until that thread's next call into the library. */
+const char* fdk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDK_H_ */

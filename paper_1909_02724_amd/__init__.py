@@ -1,0 +1,241 @@
+"""MI355X-native FDK cone-beam back-projection (after iFDK, Chen et al., SC'19).
+
+Thin ctypes binding over libfdk.so (C ABI in include/fdk.h). Every step of
+the path runs in the library's HIP kernels; PyTorch only provides device
+memory and the current stream. There is no CPU fallback: if libfdk.so is
+missing, every call raises.
+
+Arrays: volume (Nz_local, Ny, Nx) float32, x fastest; projections
+(nviews, Nv, Nu), u fastest, float32 / float16 / bfloat16 storage.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+__all__ = [
+    "Geometry", "FDKError", "lib", "backproject", "forward_project", "filter",
+    "fdk_scale", "FDKBackprojection", "fdk_backprojection",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdk.so")
+
+FDK_OK, FDK_ERR_INVALID_ARG, FDK_ERR_UNSUPPORTED, FDK_ERR_HIP, FDK_ERR_OOM = range(5)
+FDK_ACCUMULATE = 1
+_DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
+_FILTERS = {"ramlak": 0, "ram-lak": 0, "shepp-logan": 1, "shepplogan": 1}
+_SLABS = {"contiguous": 0, "mirror_pair": 1}
+
+
+@dataclass(frozen=True)
+class Geometry:
+    """Circular cone-beam geometry (Table 1 of the paper); one length unit.
+
+    nx, ny, nz: voxels; dx, dy, dz: voxel pitch; nu, nv: detector pixels;
+    du, dv: pixel pitch; off_u, off_v: principal-point shift in pixels;
+    sod: source to rotation axis (d); sdd: source to detector (D)."""
+    nx: int
+    ny: int
+    nz: int
+    nu: int
+    nv: int
+    sod: float
+    sdd: float
+    dx: float = 1.0
+    dy: float = 1.0
+    dz: float = 1.0
+    du: float = 1.0
+    dv: float = 1.0
+    off_u: float = 0.0
+    off_v: float = 0.0
+
+
+class _CGeometry(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+        ("nu", C.c_int32), ("nv", C.c_int32),
+        ("du", C.c_double), ("dv", C.c_double),
+        ("off_u", C.c_double), ("off_v", C.c_double),
+        ("sod", C.c_double), ("sdd", C.c_double),
+        ("np", C.c_int32), ("angles", C.POINTER(C.c_double)),
+    ]
+
+
+class FDKError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fdk status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libfdk.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1909_02724_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER(_CGeometry)
+        L.fdk_backproject.restype = C.c_int
+        L.fdk_backproject.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_int, C.c_void_p,
+                                      C.c_int32, C.c_int32, C.c_int, C.c_float, C.c_uint32,
+                                      C.c_void_p]
+        L.fdk_forward_project.restype = C.c_int
+        L.fdk_forward_project.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+                                          C.c_int32, C.c_int, C.c_void_p, C.c_float, C.c_uint32,
+                                          C.c_void_p]
+        L.fdk_filter.restype = C.c_int
+        L.fdk_filter.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int,
+                                 C.c_int, C.c_void_p]
+        L.fdk_fdk_scale.restype = C.c_double
+        L.fdk_fdk_scale.argtypes = [P]
+        L.fdk_last_error.restype = C.c_char_p
+        L.fdk_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _cgeom(geom, angles):
+    ang = np.ascontiguousarray(np.asarray(angles, dtype=np.float64))
+    cg = _CGeometry(int(geom.nx), int(geom.ny), int(geom.nz),
+                    float(geom.dx), float(geom.dy), float(geom.dz),
+                    int(geom.nu), int(geom.nv), float(geom.du), float(geom.dv),
+                    float(geom.off_u), float(geom.off_v), float(geom.sod), float(geom.sdd),
+                    int(ang.size), ang.ctypes.data_as(C.POINTER(C.c_double)))
+    return cg, ang  # keep `ang` alive for the duration of the call
+
+
+def _check(status: int):
+    if status != FDK_OK:
+        raise FDKError(status, lib().fdk_last_error().decode())
+
+
+def _stream(t: torch.Tensor):
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (no CPU fallback)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _slab(geom, z0, nz_local, slab):
+    nz_local = geom.nz - z0 if nz_local is None else nz_local
+    return int(z0), int(nz_local), _SLABS[slab]
+
+
+def backproject(q: torch.Tensor, geom, angles, *, view0: int = 0, out: torch.Tensor | None = None,
+                z0: int = 0, nz_local: int | None = None, slab: str = "contiguous",
+                scale: float = 1.0, accumulate: bool = False) -> torch.Tensor:
+    """Back-project views [view0, view0 + q.shape[0]) of `q` (nviews, Nv, Nu)
+    into a (nz_local, Ny, Nx) float32 slab: Alg. 2 computed as Alg. 4."""
+    _dev(q, "q")
+    if q.dtype not in _DTYPES:
+        raise ValueError(f"unsupported projection dtype {q.dtype}")
+    if q.dim() != 3 or q.shape[1:] != (geom.nv, geom.nu):
+        raise ValueError(f"q must be (nviews, {geom.nv}, {geom.nu}), got {tuple(q.shape)}")
+    z0, nzl, sk = _slab(geom, z0, nz_local, slab)
+    if out is None:
+        out = torch.empty((nzl, geom.ny, geom.nx), dtype=torch.float32, device=q.device)
+        accumulate = False
+    _dev(out, "out")
+    if out.dtype != torch.float32 or tuple(out.shape) != (nzl, geom.ny, geom.nx):
+        raise ValueError(f"out must be float32 ({nzl}, {geom.ny}, {geom.nx})")
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_backproject(C.byref(cg), view0, q.shape[0], C.c_void_p(q.data_ptr()),
+                                 _DTYPES[q.dtype], C.c_void_p(out.data_ptr()), z0, nzl, sk,
+                                 float(scale), FDK_ACCUMULATE if accumulate else 0, _stream(q)))
+    return out
+
+
+def forward_project(vol: torch.Tensor, geom, angles, *, view0: int = 0,
+                    nviews: int | None = None, out: torch.Tensor | None = None, z0: int = 0,
+                    slab: str = "contiguous", scale: float = 1.0,
+                    accumulate: bool = False) -> torch.Tensor:
+    """Matched forward projection (exact adjoint of backproject) of a
+    float32 slab into (nviews, Nv, Nu) float32 projections."""
+    _dev(vol, "vol")
+    if vol.dtype != torch.float32 or vol.dim() != 3 or vol.shape[1:] != (geom.ny, geom.nx):
+        raise ValueError(f"vol must be float32 (nz_local, {geom.ny}, {geom.nx})")
+    nviews = len(angles) - view0 if nviews is None else nviews
+    z0, nzl, sk = _slab(geom, z0, vol.shape[0], slab)
+    if out is None:
+        out = torch.empty((nviews, geom.nv, geom.nu), dtype=torch.float32, device=vol.device)
+        accumulate = False
+    _dev(out, "out")
+    if out.dtype != torch.float32 or tuple(out.shape) != (nviews, geom.nv, geom.nu):
+        raise ValueError(f"out must be float32 ({nviews}, {geom.nv}, {geom.nu})")
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_forward_project(C.byref(cg), view0, nviews, C.c_void_p(vol.data_ptr()), z0,
+                                     nzl, sk, C.c_void_p(out.data_ptr()), float(scale),
+                                     FDK_ACCUMULATE if accumulate else 0, _stream(vol)))
+    return out
+
+
+def filter(e: torch.Tensor, geom, angles, *, view0: int = 0, kind: str = "ramlak",
+           dtype: torch.dtype = torch.float32, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Filtering stage (Alg. 1): cosine weight and ramp convolution of
+    float32 line integrals (nviews, Nv, Nu); output in `dtype` storage."""
+    _dev(e, "e")
+    if e.dtype != torch.float32 or e.dim() != 3 or e.shape[1:] != (geom.nv, geom.nu):
+        raise ValueError(f"e must be float32 (nviews, {geom.nv}, {geom.nu})")
+    if out is None:
+        out = torch.empty(e.shape, dtype=dtype, device=e.device)
+    _dev(out, "out")
+    if out.dtype not in _DTYPES or out.shape != e.shape:
+        raise ValueError("out must match e's shape with a float32/float16/bfloat16 dtype")
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_filter(C.byref(cg), view0, e.shape[0], C.c_void_p(e.data_ptr()),
+                            C.c_void_p(out.data_ptr()), _DTYPES[out.dtype], _FILTERS[kind],
+                            _stream(e)))
+    return out
+
+
+def fdk_scale(geom, angles) -> float:
+    """pi d^2 / Np, the FDK constant for a full circular scan."""
+    cg, _keep = _cgeom(geom, angles)
+    return lib().fdk_fdk_scale(C.byref(cg))
+
+
+class FDKBackprojection(torch.autograd.Function):
+    """Differentiable back-projection. forward: q (B, nviews, Nv, Nu) or
+    (nviews, Nv, Nu) -> volume (B, Nz, Ny, Nx) / (Nz, Ny, Nx). backward: the
+    matched forward projector applied to the incoming volume gradient, which
+    recomputes every coordinate rather than storing them."""
+
+    @staticmethod
+    def forward(ctx, q, geom, angles, scale=1.0):
+        ctx.geom, ctx.angles, ctx.scale = geom, np.asarray(angles, np.float64), float(scale)
+        ctx.qshape, ctx.qdtype = q.shape, q.dtype
+        batched = q.dim() == 4
+        qs = q if batched else q.unsqueeze(0)
+        vols = [backproject(qs[b].contiguous(), geom, ctx.angles, scale=ctx.scale)
+                for b in range(qs.shape[0])]
+        out = torch.stack(vols)
+        return out if batched else out[0]
+
+    @staticmethod
+    def backward(ctx, gvol):
+        batched = gvol.dim() == 4
+        gv = gvol if batched else gvol.unsqueeze(0)
+        gq = torch.stack([forward_project(gv[b].to(torch.float32).contiguous(), ctx.geom,
+                                          ctx.angles, scale=ctx.scale)
+                          for b in range(gv.shape[0])])
+        gq = gq if batched else gq[0]
+        return gq.to(ctx.qdtype), None, None, None
+
+
+def fdk_backprojection(q, geom, angles, scale=1.0):
+    return FDKBackprojection.apply(q, geom, angles, scale)

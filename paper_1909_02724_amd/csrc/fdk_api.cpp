@@ -1,0 +1,292 @@
+// Host front end of the C ABI declared in include/fdk.h: argument
+// validation, per-view FP64 geometry, slab decomposition into slice runs
+// and kernel dispatch on the caller's stream. Nothing here touches the HIP
+// runtime until every argument has been validated.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "fdk_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fdk_status fail(fdk_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+fdk_status ok() {
+  g_last_error.clear();
+  return FDK_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Largest |u - cu| or |v - cv| (pixels) allowed, so that pixel indices and
+// LDS/tap offsets stay well inside int32 arithmetic.
+constexpr double kMaxCoord = 4194304.0;  // 2^22
+
+fdk_status check_geometry(const fdk_geometry* g) {
+  if (!g) return fail(FDK_ERR_INVALID_ARG, "geometry pointer is NULL");
+  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0)
+    return fail(FDK_ERR_INVALID_ARG, "volume size must be positive (got %d x %d x %d)", g->nx,
+                g->ny, g->nz);
+  if (g->nu <= 0 || g->nv <= 0)
+    return fail(FDK_ERR_INVALID_ARG, "detector size must be positive (got %d x %d)", g->nu, g->nv);
+  if ((int64_t)g->nu * g->nv > (int64_t)1 << 30)
+    return fail(FDK_ERR_INVALID_ARG, "detector of %d x %d pixels is too large", g->nu, g->nv);
+  if ((int64_t)g->nx * g->ny > (int64_t)1 << 30)
+    return fail(FDK_ERR_INVALID_ARG, "volume slice of %d x %d voxels is too large", g->nx, g->ny);
+  if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz))
+    return fail(FDK_ERR_INVALID_ARG, "voxel pitch must be positive and finite");
+  if (!finite_pos(g->du) || !finite_pos(g->dv))
+    return fail(FDK_ERR_INVALID_ARG, "pixel pitch must be positive and finite");
+  if (!std::isfinite(g->off_u) || !std::isfinite(g->off_v))
+    return fail(FDK_ERR_INVALID_ARG, "principal-point offsets must be finite");
+  if (!finite_pos(g->sod) || !finite_pos(g->sdd))
+    return fail(FDK_ERR_INVALID_ARG, "sod and sdd must be positive and finite");
+  if (g->np <= 0) return fail(FDK_ERR_INVALID_ARG, "np must be positive (got %d)", g->np);
+  if (!g->angles) return fail(FDK_ERR_INVALID_ARG, "angles pointer is NULL");
+  // Eq. 3: z = d + sin(b) X + cos(b) Y; its minimum over the voxel centres
+  // is at least d minus the half-diagonal of the x-y grid of centres.
+  const double r = 0.5 * std::hypot((g->nx - 1) * g->dx, (g->ny - 1) * g->dy);
+  const double zmin = g->sod - r;
+  if (!(zmin > 1e-6 * g->sod))
+    return fail(FDK_ERR_INVALID_ARG,
+                "sod = %g does not exceed the volume's x-y half-diagonal %g: some voxel has z <= 0",
+                g->sod, r);
+  const double umax = std::fabs((g->nu - 1) * 0.5 + g->off_u) + g->sdd / g->du * r / zmin;
+  const double vmax = std::fabs((g->nv - 1) * 0.5 + g->off_v) +
+                      g->sdd * g->dz / g->dv * (0.5 * (g->nz - 1)) / zmin;
+  if (!(umax < kMaxCoord) || !(vmax < kMaxCoord))
+    return fail(FDK_ERR_INVALID_ARG, "geometry maps voxels too far off the detector (%g, %g px)",
+                umax, vmax);
+  return FDK_OK;
+}
+
+fdk_status check_views(const fdk_geometry* g, int32_t view0, int32_t nviews) {
+  if (view0 < 0 || nviews < 0 || (int64_t)view0 + nviews > g->np)
+    return fail(FDK_ERR_INVALID_ARG, "view range [%d, %d + %d) is outside [0, %d)", view0, view0,
+                nviews, g->np);
+  for (int32_t s = view0; s < view0 + nviews; ++s)
+    if (!std::isfinite(g->angles[s]))
+      return fail(FDK_ERR_INVALID_ARG, "angle of view %d is not finite", s);
+  return FDK_OK;
+}
+
+fdk::GeoConst make_geo(const fdk_geometry* g) {
+  fdk::GeoConst gc;
+  gc.nx = g->nx;
+  gc.ny = g->ny;
+  gc.nz = g->nz;
+  gc.nu = g->nu;
+  gc.nv = g->nv;
+  gc.cu = 0.5 * (g->nu - 1) + g->off_u;
+  gc.cv = 0.5 * (g->nv - 1) + g->off_v;
+  gc.cz = 0.5 * (g->nz - 1);
+  gc.ku = g->sdd / g->du;
+  gc.kv = g->sdd * g->dz / g->dv;
+  // Theorem 1 with a shifted principal point: v(Nz-1-k) = 2 cv - v(k). The
+  // mirrored taps line up with whole pixels only when 2 cv is an integer.
+  const double G = (g->nv - 1) + 2.0 * g->off_v;
+  gc.mirror_g = (std::fabs(G - std::nearbyint(G)) <= 1e-9) ? (int32_t)std::nearbyint(G) : INT32_MIN;
+  return gc;
+}
+
+// Eq. 2 expanded for one gantry angle: world X = Dx (i - cx), Y = -Dy (j - cy);
+// after the rotation, z = d + sin(b) X + cos(b) Y and a = cos(b) X - sin(b) Y.
+fdk::ViewGeo make_view(const fdk_geometry* g, double beta) {
+  const double s = std::sin(beta), c = std::cos(beta);
+  const double cx = 0.5 * (g->nx - 1), cy = 0.5 * (g->ny - 1);
+  fdk::ViewGeo v;
+  v.ci = s * g->dx;
+  v.cj = -c * g->dy;
+  v.c0 = g->sod - s * g->dx * cx + c * g->dy * cy;
+  v.ai = c * g->dx;
+  v.aj = s * g->dy;
+  v.a0 = -c * g->dx * cx - s * g->dy * cy;
+  return v;
+}
+
+struct Slab {
+  std::vector<fdk::SliceRun> runs;
+};
+
+// Split the slab's slices into mirrored pairs (Theorem 1, Alg. 4's k < Nz/2
+// loop) and plain runs for slices without an in-slab mirror.
+fdk_status make_slab(const fdk_geometry* g, const fdk::GeoConst& gc, int32_t z0, int32_t nzl,
+                     fdk_slab_kind kind, Slab* out) {
+  const int32_t nz = g->nz;
+  if (kind != FDK_SLAB_CONTIGUOUS && kind != FDK_SLAB_MIRROR_PAIR)
+    return fail(FDK_ERR_UNSUPPORTED, "unknown slab kind %d", (int)kind);
+  if (z0 < 0 || nzl <= 0) return fail(FDK_ERR_INVALID_ARG, "slab z0 = %d, nz_local = %d", z0, nzl);
+  const bool can_mirror = gc.mirror_g != INT32_MIN;
+  std::vector<int32_t> loc(nz, -1);  // global slice -> slab slice
+  if (kind == FDK_SLAB_CONTIGUOUS) {
+    if ((int64_t)z0 + nzl > nz)
+      return fail(FDK_ERR_INVALID_ARG, "slab [%d, %d) exceeds Nz = %d", z0, z0 + nzl, nz);
+    for (int32_t t = 0; t < nzl; ++t) loc[z0 + t] = t;
+  } else {
+    if (nzl % 2) return fail(FDK_ERR_INVALID_ARG, "mirror-pair slab needs an even nz_local");
+    const int32_t h = nzl / 2;
+    if ((int64_t)z0 + h > (int64_t)nz - z0 - h)
+      return fail(FDK_ERR_INVALID_ARG, "mirror-pair halves [%d, %d) and [%d, %d) overlap", z0,
+                  z0 + h, nz - z0 - h, nz - z0);
+    for (int32_t t = 0; t < h; ++t) {
+      loc[z0 + t] = t;
+      loc[nz - z0 - h + t] = h + t;
+    }
+  }
+  std::vector<char> done(nz, 0);
+  out->runs.clear();
+  // Mirrored pairs: lower slice k < Nz/2 whose mirror is also held, both
+  // slab-contiguous in the directions the kernel walks.
+  if (can_mirror) {
+    int32_t k = 0;
+    while (k < nz / 2) {
+      if (loc[k] < 0 || loc[nz - 1 - k] < 0) {
+        ++k;
+        continue;
+      }
+      fdk::SliceRun r{k, 1, loc[k], loc[nz - 1 - k], 1};
+      while (k + r.n < nz / 2 && loc[k + r.n] == r.loc_lo + r.n &&
+             loc[nz - 1 - k - r.n] == r.loc_hi - r.n)
+        ++r.n;
+      for (int32_t t = 0; t < r.n; ++t) done[k + t] = done[nz - 1 - k - t] = 1;
+      out->runs.push_back(r);
+      k += r.n;
+    }
+  }
+  for (int32_t k = 0; k < nz;) {
+    if (loc[k] < 0 || done[k]) {
+      ++k;
+      continue;
+    }
+    fdk::SliceRun r{k, 1, loc[k], loc[k], 0};
+    while (k + r.n < nz && loc[k + r.n] == r.loc_lo + r.n && !done[k + r.n]) ++r.n;
+    out->runs.push_back(r);
+    k += r.n;
+  }
+  return FDK_OK;
+}
+
+size_t dtype_size(fdk_dtype t) { return t == FDK_F32 ? 4 : 2; }
+
+}  // namespace
+
+extern "C" {
+
+const char* fdk_last_error(void) { return g_last_error.c_str(); }
+
+double fdk_fdk_scale(const fdk_geometry* g) {
+  if (!g || g->np <= 0 || !std::isfinite(g->sod)) return std::nan("");
+  return M_PI * g->sod * g->sod / g->np;
+}
+
+fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews, const void* q,
+                           fdk_dtype q_dtype, float* vol, int32_t z0, int32_t nz_local,
+                           fdk_slab_kind slab, float scale, uint32_t flags, void* stream) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if ((st = check_views(g, view0, nviews))) return st;
+  if (q_dtype != FDK_F32 && q_dtype != FDK_F16 && q_dtype != FDK_BF16)
+    return fail(FDK_ERR_UNSUPPORTED, "unknown projection dtype %d", (int)q_dtype);
+  if (!vol) return fail(FDK_ERR_INVALID_ARG, "volume pointer is NULL");
+  if (nviews > 0 && !q) return fail(FDK_ERR_INVALID_ARG, "projection pointer is NULL");
+  if (!std::isfinite(scale)) return fail(FDK_ERR_INVALID_ARG, "scale is not finite");
+  if (flags & ~FDK_ACCUMULATE) return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  const fdk::GeoConst gc = make_geo(g);
+  Slab sl;
+  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  const bool acc0 = flags & FDK_ACCUMULATE;
+  const int64_t slice = (int64_t)g->nx * g->ny;
+  if (nviews == 0) {
+    if (!acc0) {
+      if (int e = fdk::launch_fill_zero(vol, slice * nz_local, stream))
+        return fail(FDK_ERR_HIP, "zero fill failed: HIP error %d", e);
+    }
+    return ok();
+  }
+  const int64_t vstride = (int64_t)g->nu * g->nv;
+  fdk::ViewBatch vb;
+  for (int32_t b = 0; b < nviews; b += fdk::kMaxViewsPerLaunch) {
+    vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
+    for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
+    const char* qb = static_cast<const char*>(q) + (size_t)b * vstride * dtype_size(q_dtype);
+    for (const fdk::SliceRun& r : sl.runs) {
+      if (int e = fdk::launch_backproject(gc, r, vb, qb, q_dtype, vstride, vol, scale,
+                                          (b > 0) || acc0, stream))
+        return fail(FDK_ERR_HIP, "back-projection launch failed: HIP error %d", e);
+    }
+  }
+  return ok();
+}
+
+fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                               const float* vol, int32_t z0, int32_t nz_local,
+                               fdk_slab_kind slab, float* q, float scale, uint32_t flags,
+                               void* stream) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if ((st = check_views(g, view0, nviews))) return st;
+  if (!vol) return fail(FDK_ERR_INVALID_ARG, "volume pointer is NULL");
+  if (nviews > 0 && !q) return fail(FDK_ERR_INVALID_ARG, "projection pointer is NULL");
+  if (!std::isfinite(scale)) return fail(FDK_ERR_INVALID_ARG, "scale is not finite");
+  if (flags & ~FDK_ACCUMULATE) return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  const fdk::GeoConst gc = make_geo(g);
+  Slab sl;
+  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  if (nviews == 0) return ok();
+  const int64_t vstride = (int64_t)g->nu * g->nv;
+  if (!(flags & FDK_ACCUMULATE)) {
+    if (int e = fdk::launch_fill_zero(q, vstride * nviews, stream))
+      return fail(FDK_ERR_HIP, "zero fill failed: HIP error %d", e);
+  }
+  fdk::ViewBatch vb;
+  for (int32_t b = 0; b < nviews; b += fdk::kMaxViewsPerLaunch) {
+    vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
+    for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
+    for (const fdk::SliceRun& r : sl.runs) {
+      if (int e = fdk::launch_forward_project(gc, r, vb, vol, q + (size_t)b * vstride, vstride,
+                                              scale, stream))
+        return fail(FDK_ERR_HIP, "forward-projection launch failed: HIP error %d", e);
+    }
+  }
+  return ok();
+}
+
+fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews, const float* e,
+                      void* q, fdk_dtype out_dtype, fdk_filter_kind kind, void* stream) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if ((st = check_views(g, view0, nviews))) return st;
+  if (out_dtype != FDK_F32 && out_dtype != FDK_F16 && out_dtype != FDK_BF16)
+    return fail(FDK_ERR_UNSUPPORTED, "unknown output dtype %d", (int)out_dtype);
+  if (kind != FDK_RAMLAK && kind != FDK_SHEPP_LOGAN)
+    return fail(FDK_ERR_UNSUPPORTED, "unknown filter kind %d", (int)kind);
+  if (g->nu > 8192) return fail(FDK_ERR_UNSUPPORTED, "filter rows above 8192 pixels (Nu = %d)", g->nu);
+  if (nviews == 0) return ok();
+  if (!e || !q) return fail(FDK_ERR_INVALID_ARG, "projection pointer is NULL");
+  const size_t nbytes_in = (size_t)nviews * g->nv * g->nu * 4;
+  const size_t nbytes_out = (size_t)nviews * g->nv * g->nu * dtype_size(out_dtype);
+  const char* a = reinterpret_cast<const char*>(e);
+  const char* b = static_cast<const char*>(q);
+  if (a < b + nbytes_out && b < a + nbytes_in)
+    return fail(FDK_ERR_INVALID_ARG, "filter input and output overlap");
+  const fdk::GeoConst gc = make_geo(g);
+  if (int err = fdk::launch_filter(gc, g->du, g->dv, g->sod, g->sdd, nviews * g->nv, e, q,
+                                   out_dtype, kind, stream))
+    return fail(FDK_ERR_HIP, "filter launch failed: HIP error %d", err);
+  return ok();
+}
+
+}  // extern "C"

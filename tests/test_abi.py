@@ -1,0 +1,120 @@
+"""CPU checks of the C ABI: the library loads, exports every function its
+header declares, lays out fdk_geometry as C does, and rejects invalid
+arguments on the host with the documented status and a message, before
+any HIP call (so these run without a GPU)."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1909_02724_amd as fdk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdk_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = fdk.lib()
+    names = declared_functions()
+    assert {"fdk_filter", "fdk_backproject", "fdk_forward_project", "fdk_fdk_scale",
+            "fdk_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", fdk.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (fdk_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_geometry_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "fdk.h"\n'
+        "int main(void){printf(\"%zu\", sizeof(fdk_geometry));\n"
+        + "".join(f'printf(" %zu", offsetof(fdk_geometry, {f}));\n'
+                  for f, _ in fdk._CGeometry._fields_)
+        + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(fdk._CGeometry)
+    assert vals[1:] == [getattr(fdk._CGeometry, f).offset for f, _ in fdk._CGeometry._fields_]
+
+
+GOOD = fdk.Geometry(nx=16, ny=16, nz=8, nu=24, nv=20, sod=100.0, sdd=200.0, du=2.0, dv=2.0)
+ANG = np.linspace(0, 2 * math.pi, 12, endpoint=False)
+FAKE = C.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def call_bp(g=GOOD, ang=ANG, view0=0, nviews=4, q=FAKE, dtype=0, vol=FAKE, z0=0, nzl=8,
+            slab=0, scale=1.0, flags=0):
+    cg, keep = fdk._cgeom(g, ang)
+    st = fdk.lib().fdk_backproject(C.byref(cg), view0, nviews, q, dtype, vol, z0, nzl, slab,
+                                   scale, flags, None)
+    return st, fdk.lib().fdk_last_error().decode()
+
+
+@pytest.mark.parametrize("kw, status, msg", [
+    (dict(g=GOOD.__class__(**{**GOOD.__dict__, "nx": 0})), 1, "volume size"),
+    (dict(g=GOOD.__class__(**{**GOOD.__dict__, "dv": -1.0})), 1, "pixel pitch"),
+    (dict(g=GOOD.__class__(**{**GOOD.__dict__, "sod": 10.0})), 1, "half-diagonal"),
+    (dict(g=GOOD.__class__(**{**GOOD.__dict__, "sdd": float("nan")})), 1, "sod and sdd"),
+    (dict(ang=np.array([0.0, float("inf"), 1.0, 2.0])), 1, "not finite"),
+    (dict(view0=10, nviews=4), 1, "view range"),
+    (dict(view0=-1), 1, "view range"),
+    (dict(q=None), 1, "projection pointer"),
+    (dict(vol=None), 1, "volume pointer"),
+    (dict(dtype=7), 2, "dtype"),
+    (dict(z0=4, nzl=8), 1, "exceeds"),
+    (dict(nzl=0), 1, "nz_local"),
+    (dict(slab=1, nzl=5), 1, "even"),
+    (dict(slab=1, z0=2, nzl=8), 1, "overlap"),
+    (dict(slab=3), 2, "slab kind"),
+    (dict(scale=float("nan")), 1, "scale"),
+    (dict(flags=4), 1, "flags"),
+])
+def test_backproject_validation(kw, status, msg):
+    st, err = call_bp(**kw)
+    assert st == status and msg in err, (st, err)
+
+
+def test_forward_and_filter_validation():
+    L = fdk.lib()
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    assert L.fdk_forward_project(C.byref(cg), 0, 4, None, 0, 8, 0, FAKE, 1.0, 0, None) == 1
+    assert "volume pointer" in L.fdk_last_error().decode()
+    assert L.fdk_forward_project(C.byref(cg), 11, 4, FAKE, 0, 8, 0, FAKE, 1.0, 0, None) == 1
+    assert L.fdk_filter(C.byref(cg), 0, 4, FAKE, FAKE, 0, 9, None) == 2
+    assert "filter kind" in L.fdk_last_error().decode()
+    assert L.fdk_filter(C.byref(cg), 0, 4, FAKE, FAKE, 5, 0, None) == 2
+    assert L.fdk_filter(C.byref(cg), 0, 4, C.c_void_p(0x1000), C.c_void_p(0x1004), 0, 0, None) == 1
+    assert "overlap" in L.fdk_last_error().decode()
+    wide = GOOD.__class__(**{**GOOD.__dict__, "nu": 9000})
+    cw, keep2 = fdk._cgeom(wide, ANG)
+    assert L.fdk_filter(C.byref(cw), 0, 4, FAKE, C.c_void_p(0x10000000), 0, 0, None) == 2
+    assert L.fdk_backproject(None, 0, 1, FAKE, 0, FAKE, 0, 8, 0, 1.0, 0, None) == 1
+    assert "NULL" in L.fdk_last_error().decode()
+
+
+def test_fdk_scale():
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    assert fdk.lib().fdk_fdk_scale(C.byref(cg)) == pytest.approx(math.pi * 100.0 ** 2 / 12)
+    assert math.isnan(fdk.lib().fdk_fdk_scale(None))
+
+
+def test_python_layer_refuses_cpu_tensors():
+    import torch
+    with pytest.raises(ValueError, match="GPU tensor"):
+        fdk.backproject(torch.zeros(4, 20, 24), GOOD, ANG)

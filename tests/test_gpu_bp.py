@@ -1,0 +1,238 @@
+"""GPU parity of the HIP back-projector and its adjoint against the FP64 CPU
+oracle, through the C ABI (via the thin Python binding).
+
+Inputs come from the seeded generators in `synth` or from the oracle itself;
+nothing the GPU computes is ever fed to the oracle. Tolerances (rel-L2 in
+FP64): 1e-5 for FP32 storage against the oracle on identical inputs; the
+same 1e-5 for 16-bit storage against the oracle fed the identically rounded
+values; 2e-3 for 16-bit storage against the unrounded FP32 inputs; 1e-5 for
+the adjoint dot-product identity."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+fdk = pytest.importorskip("paper_1909_02724_amd")
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def rel_l2(got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def gpu(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+def announce(msg):
+    print(msg, flush=True)
+
+
+BASE = synth.Geom(nx=70, ny=45, nz=38, nu=80, nv=56, sod=420.0, sdd=760.0, du=1.5, dv=1.5)
+VARIANTS = {
+    "ragged_even": BASE,
+    "ragged_odd": BASE.replace(nz=37),
+    "offset_half": BASE.replace(off_u=0.3, off_v=0.5),     # 2 c_v integer: mirrored
+    "offset_frac": BASE.replace(off_u=-0.7, off_v=0.27),   # no pixel-aligned mirror: plain
+    "anisotropic": BASE.replace(dx=0.8, dy=1.1, dz=1.3, du=1.2, dv=1.7, nu=96, nv=50),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+@pytest.mark.parametrize("smooth", [False, True])
+def test_bp_full_volume_matches_oracle(name, smooth):
+    g = VARIANTS[name]
+    ang = synth.angles(45, start=0.1)   # 45 views: one launch of 32 and one of 13
+    q = synth.random_projections(11, 45, g, smooth=smooth)
+    announce(f"bp {name} smooth={smooth} geom={g}")
+    vol = fdk.backproject(gpu(q), g, ang, scale=0.37)
+    torch.cuda.synchronize()
+    ref = oracle.backproject(g, ang, q.astype(np.float64), scale=0.37)
+    err = rel_l2(host(vol), ref)
+    announce(f"  rel-L2 = {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_fdk64_pipeline():
+    """64^3, 64 views of 64^2, 8 ellipsoids, Ram-Lak: the GPU filter and the
+    GPU back-projection each match the oracle on identical inputs, and the
+    whole GPU FDK matches the oracle's FDK."""
+    c = synth.config("fdk64")
+    g = c["geom"]
+    ang = synth.angles(c["np"])
+    ell = synth.ellipsoids(c["seed"], c["n_ell"], g)
+    announce("fdk64 pipeline")
+    e32 = oracle.phantom_project(g, ang, ell).astype(np.float32)
+    q_ref = oracle.filter(g, e32.astype(np.float64), "ramlak")
+    q_gpu = fdk.filter(gpu(e32), g, ang, kind="ramlak")
+    assert rel_l2(host(q_gpu), q_ref) <= 1e-5
+    scale = oracle.fdk_scale(g, len(ang))
+    assert fdk.fdk_scale(g, ang) == pytest.approx(scale, rel=1e-15)
+    q32 = q_ref.astype(np.float32)
+    vol = fdk.backproject(gpu(q32), g, ang, scale=scale)
+    ref = oracle.backproject(g, ang, q32.astype(np.float64), scale=scale)
+    assert rel_l2(host(vol), ref) <= 1e-5
+    full = fdk.backproject(fdk.filter(gpu(e32), g, ang, kind="ramlak"), g, ang, scale=scale)
+    ref_full = oracle.backproject(g, ang, q_ref, scale=scale)
+    err = rel_l2(host(full), ref_full)
+    announce(f"  end-to-end FDK rel-L2 = {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["ramlak", "shepp-logan"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16, torch.bfloat16])
+def test_filter_matches_oracle(kind, dtype):
+    g = BASE.replace(nu=333, nv=7, off_u=0.4)
+    ang = synth.angles(3)
+    e = np.random.default_rng(4).uniform(0, 50, (3, g.nv, g.nu)).astype(np.float32)
+    ref = oracle.filter(g, e.astype(np.float64), kind)
+    got = host(fdk.filter(gpu(e), g, ang, kind=kind, dtype=dtype))
+    tol = {torch.float32: 1e-5, torch.float16: 1e-3, torch.bfloat16: 8e-3}[dtype]
+    assert rel_l2(got, ref) <= tol
+
+
+SLABS = [
+    ("contiguous", 0, 38),    # whole volume
+    ("contiguous", 5, 20),    # [5, 25): paired 13..24 with 13..24? mixed paired/plain
+    ("contiguous", 20, 18),   # upper part only: all plain
+    ("contiguous", 3, 32),    # [3, 35): fully paired around the centre
+    ("mirror_pair", 0, 12),   # [0, 6) + [32, 38)
+    ("mirror_pair", 7, 10),   # [7, 12) + [26, 31)
+]
+
+
+@pytest.mark.parametrize("slab, z0, nzl", SLABS)
+def test_bp_slabs(slab, z0, nzl):
+    g = BASE
+    ang = synth.angles(20, start=0.3)
+    q = synth.random_projections(12, 20, g)
+    if slab == "contiguous":
+        ks = np.arange(z0, z0 + nzl)
+    else:
+        h = nzl // 2
+        ks = np.concatenate([np.arange(z0, z0 + h), np.arange(g.nz - z0 - h, g.nz - z0)])
+    announce(f"slab {slab} z0={z0} nz_local={nzl}")
+    vol = fdk.backproject(gpu(q), g, ang, z0=z0, nz_local=nzl, slab=slab)
+    full = oracle.backproject(g, ang, q.astype(np.float64))
+    assert rel_l2(host(vol), full[ks]) <= 1e-5
+    x = np.random.default_rng(3).standard_normal((nzl, g.ny, g.nx)).astype(np.float32)
+    fp = fdk.forward_project(gpu(x), g, ang, z0=z0, slab=slab)
+    xfull = np.zeros((g.nz, g.ny, g.nx))
+    xfull[ks] = x
+    fref = oracle.forward_project(g, ang, xfull)
+    assert rel_l2(host(fp), fref) <= 1e-5
+
+
+def test_accumulate_and_zero_views():
+    g = BASE.replace(nz=10)
+    ang = synth.angles(8)
+    q = synth.random_projections(13, 8, g)
+    base = np.random.default_rng(5).standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
+    out = gpu(base)
+    fdk.backproject(gpu(q[3:]), g, ang, view0=3, out=out, accumulate=True, scale=2.0)
+    ref = base + oracle.backproject(g, ang[3:], q[3:].astype(np.float64), scale=2.0)
+    assert rel_l2(host(out), ref) <= 1e-5
+    # zero views without accumulation clears the slab
+    fdk.backproject(gpu(q[:0]), g, ang, out=out)
+    assert float(out.abs().max()) == 0.0
+    # chunked accumulation equals one call
+    a = fdk.backproject(gpu(q[:3]), g, ang)
+    fdk.backproject(gpu(q[3:]), g, ang, view0=3, out=a, accumulate=True)
+    b = fdk.backproject(gpu(q), g, ang)
+    assert rel_l2(host(a), host(b)) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype,rnd", [(torch.float16, "f16"), (torch.bfloat16, "bf16")])
+def test_bp_16bit_storage(dtype, rnd):
+    g = BASE
+    ang = synth.angles(40)
+    q = synth.random_projections(14, 40, g, smooth=True)
+    qt = gpu(q, dtype)                       # round to nearest even on the host (torch)
+    q_rounded = host(qt)                     # exactly the stored values
+    # the stored values are the oracle's rounding of the FP32 inputs
+    probe = q.reshape(-1)[:2000].astype(np.float64)
+    rf = oracle.round_f16 if rnd == "f16" else oracle.round_bf16
+    assert np.array_equal(q_rounded.reshape(-1)[:2000], [rf(x) for x in probe])
+    vol = host(fdk.backproject(qt, g, ang))
+    ref_same = oracle.backproject(g, ang, q_rounded)
+    ref_f32 = oracle.backproject(g, ang, q.astype(np.float64))
+    e_same, e_f32 = rel_l2(vol, ref_same), rel_l2(vol, ref_f32)
+    announce(f"  {rnd}: vs rounded-input oracle {e_same:.3e}, vs FP32-input oracle {e_f32:.3e}")
+    assert e_same <= 1e-5
+    assert e_f32 <= 2e-3
+
+
+def test_bp_bitwise_deterministic():
+    g = BASE
+    ang = synth.angles(33)
+    q = gpu(synth.random_projections(15, 33, g))
+    a = fdk.backproject(q, g, ang)
+    b = fdk.backproject(q, g, ang)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["ragged_even", "ragged_odd", "offset_half", "offset_frac"])
+def test_adjoint_matches_oracle_and_dot_test(name):
+    g = VARIANTS[name]
+    ang = synth.angles(37, start=0.2)
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
+    q = rng.standard_normal((37, g.nv, g.nu)).astype(np.float32)
+    fp = fdk.forward_project(gpu(x), g, ang, scale=0.8)
+    ref = oracle.forward_project(g, ang, x.astype(np.float64), scale=0.8)
+    assert rel_l2(host(fp), ref) <= 1e-5
+    bp = fdk.backproject(gpu(q), g, ang, scale=0.8)
+    lhs = float(np.vdot(host(bp), x.astype(np.float64)))
+    rhs = float(np.vdot(q.astype(np.float64), host(fp)))
+    announce(f"  dot test {name}: {lhs:.9e} vs {rhs:.9e}")
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_autograd_backward_is_matched_projector():
+    g = BASE.replace(nz=16)
+    ang = synth.angles(24)
+    rng = np.random.default_rng(31)
+    q = gpu(rng.standard_normal((2, 24, g.nv, g.nu)).astype(np.float32)).requires_grad_(True)
+    w = gpu(rng.standard_normal((2, g.nz, g.ny, g.nx)).astype(np.float32))
+    vol = fdk.fdk_backprojection(q, g, ang, 0.5)
+    (vol * w).sum().backward()
+    for b in range(2):
+        ref = oracle.forward_project(g, ang, host(w[b]), scale=0.5)
+        assert rel_l2(host(q.grad[b]), ref) <= 1e-5
+    # finite differences: the map is linear, so they differ only by rounding
+    d = gpu(rng.standard_normal((2, 24, g.nv, g.nu)).astype(np.float32))
+    with torch.no_grad():
+        lp = float((fdk.fdk_backprojection(q + d, g, ang, 0.5).double() * w.double()).sum())
+        lm = float((fdk.fdk_backprojection(q - d, g, ang, 0.5).double() * w.double()).sum())
+    fd = (lp - lm) / 2.0
+    an = float((q.grad.double() * d.double()).sum())
+    assert abs(fd - an) <= 1e-5 * abs(an)
+
+
+def test_synth_gpu_generators_match_oracle():
+    import synth.gpu as sg
+    n = 100000
+    for dtype, rnd in [(torch.float32, None), (torch.float16, "f16"), (torch.bfloat16, "bf16")]:
+        t = sg.hash_fill(torch.empty(n, dtype=dtype, device=DEV), 77, counter0=12345)
+        ref = oracle.hash_values(77, np.arange(12345, 12345 + n, dtype=np.uint64), rnd=rnd)
+        assert np.array_equal(host(t), ref), dtype
+    g = BASE
+    ang = synth.angles(6, start=0.4)
+    ell = synth.ellipsoids(3, 5, g)
+    e = host(sg.phantom_project(g, ang, ell))
+    svu = np.stack([np.random.default_rng(0).integers(0, m, 3000) for m in (6, g.nv, g.nu)], 1)
+    ref = oracle.phantom_project_pixels(g, ang, svu, ell)
+    got = e[svu[:, 0], svu[:, 1], svu[:, 2]]
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
