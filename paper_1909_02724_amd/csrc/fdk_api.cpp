@@ -223,7 +223,8 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
     for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
     const char* qb = static_cast<const char*>(q) + (size_t)b * vstride * dtype_size(q_dtype);
     for (const fdk::SliceRun& r : sl.runs) {
-      if (int e = fdk::launch_backproject(gc, r, vb, qb, q_dtype, vstride, vol, scale,
+      const fdk::TileShape ts = fdk::tile_shape(g, gc, r, vb);
+      if (int e = fdk::launch_backproject(gc, r, vb, ts, qb, q_dtype, vstride, vol, scale,
                                           (b > 0) || acc0, stream))
         return fail(FDK_ERR_HIP, "back-projection launch failed: HIP error %d", e);
     }

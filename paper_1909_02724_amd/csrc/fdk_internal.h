@@ -45,10 +45,33 @@ struct ViewBatch {
   int32_t nviews;
 };
 
+// LDS-tiled back-projection: a workgroup owns a brick of kBrickX x kBrickY
+// columns and kBrickZ voxel pairs per column; per view it stages the
+// brick's detector footprint, a tile of tu x tv pixels, into LDS, vc views
+// at a time. tu and tv are host-side upper bounds of the footprint.
+constexpr int kBrickX = 16;
+constexpr int kBrickY = 16;
+constexpr int kBrickZ = 16;
+constexpr int kMaxStageViews = 4;
+constexpr int kTileLdsBytes = 61440;
+constexpr int kTileEntryBytes = 16;  // (q, dq/du) for a row and its mirror
+
+struct TileShape {
+  int32_t tu, tv, vc;    // tile columns, rows, views staged at once (0: no tiling)
+  int32_t nbx, nby, nseg;  // bricks along x, y and z-segments in the run
+};
+
+// Kernel choice for fdk_backproject: tiled unless the footprint tile does
+// not fit the LDS budget (or the FDK_BP_KERNEL environment variable asks
+// for "direct", a debugging aid).
+TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
+                     const ViewBatch& vb);
+
 // Launchers (defined in the .hip files). They return a hipError_t as int.
 int launch_backproject(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
-                       const void* q, fdk_dtype q_dtype, int64_t view_stride,
-                       float* vol, float scale, int accumulate, void* stream);
+                       const TileShape& ts, const void* q, fdk_dtype q_dtype,
+                       int64_t view_stride, float* vol, float scale, int accumulate,
+                       void* stream);
 int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
                            const float* vol, float* q, int64_t view_stride, float scale,
                            void* stream);

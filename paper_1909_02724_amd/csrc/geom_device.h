@@ -59,11 +59,19 @@ __device__ __forceinline__ ColumnView column_view(const GeoConst& gc, const View
 }
 
 // Row index and fraction of voxel kb + t on the column: v = v(kb) + t dv/dk.
+// The offset tt is never negative (fvb >= 0, dv/dk > 0), so truncation is
+// floor and the hardware fraction is tt - floor(tt), both exact.
+__device__ __forceinline__ void voxel_row_off(float fvb, float dvk, int32_t t, uint32_t* n,
+                                              float* fr) {
+  const float tt = fmaf(static_cast<float>(t), dvk, fvb);
+  *n = static_cast<uint32_t>(tt);
+  *fr = __builtin_amdgcn_fractf(tt);
+}
+
 __device__ __forceinline__ void voxel_row(const ColumnView& c, int32_t t, int32_t* n, float* fr) {
-  const float tt = fmaf(static_cast<float>(t), c.dvk, c.fvb);
-  const float fl = floorf(tt);
-  *n = c.nvb + static_cast<int32_t>(fl);
-  *fr = tt - fl;
+  uint32_t dn;
+  voxel_row_off(c.fvb, c.dvk, t, &dn, fr);
+  *n = c.nvb + static_cast<int32_t>(dn);
 }
 
 }  // namespace fdk
