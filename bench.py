@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy a buffer of this many MiB (a plain copy of known size, "
+                         "whose HBM counters scale the kernel's)")
     return ap.parse_args()
 
 
@@ -93,6 +96,14 @@ def main():
     updates = float(g.nx) * g.ny * g.nz * n_views
     launches = math.ceil(n_views / 32)
     log(f"workload {args.workload}: {g.nx}x{g.ny}x{g.nz} volume, {n_views} views of {g.nv}x{g.nu}")
+    if args.copy_calibration:
+        n = args.copy_calibration * 2 ** 18
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_calibration} MiB read, {args.copy_calibration} MiB written")
+        del src, dst
 
     # ---- inputs: analytic phantom projections, filtered by the library ----
     t0 = time.time()

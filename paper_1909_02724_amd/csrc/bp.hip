@@ -1,24 +1,36 @@
 // Back-projection (Alg. 2 computed as Alg. 4) and its exact adjoint for
 // gfx950.
 //
-// Tiled kernel (the main path). A workgroup of 256 threads owns a brick of
-// 16 x 16 (x, y) columns and 16 consecutive slices of a slice run; for a
-// mirrored run (Theorem 1) every thread also owns the 16 mirror voxels of
-// its column. For each view the brick's detector footprint is staged into
-// LDS as a tile whose rows hold, for pixel (u, v), the value q(u, v), the
-// forward difference q(u+1, v) - q(u, v), and the same pair for the mirror
-// row G - v. With the mirror rows stored in reverse order, a voxel and its
-// mirror read the same tile offsets with the same weights, so one row
-// index, one fraction and one address serve the pair; the u-interpolation
-// is a single FMA on the staged difference (Theorem 2: u, hence the
-// fraction du, is fixed along the column). Each thread accumulates all
-// views of the launch in registers and writes every voxel once per launch;
-// lanes run along x, so volume traffic is coalesced. No atomics: every
-// voxel has one owner and a fixed summation order.
+// Work decomposition. A workgroup of 256 threads owns a brick of 16 x 16
+// (x, y) columns and 16 consecutive slices of a slice run; for a mirrored
+// run (Theorem 1) each thread also owns the 16 mirror voxels of its
+// column. Each thread accumulates every view of the launch in registers
+// and writes each voxel once per launch; lanes run along x, so volume
+// traffic is coalesced. No atomics: every voxel has one owner and a fixed
+// summation order, so results are bitwise reproducible.
 //
-// Direct kernel (fallback when a footprint tile exceeds the LDS budget):
-// the same per-column arithmetic with taps read straight from global
-// memory.
+// Coordinates. For each (brick, view) one lane evaluates, in FP64, the
+// tile origin (the floor of the smallest u and v over the brick's corners,
+// minus one pixel) and a handful of brick constants; every thread then
+// derives its column's u, v(kb), W = f^2 and dv/dk in FP32 from offsets
+// relative to the brick origin (Theorems 2 and 3: u and z, hence f, are
+// fixed along the column; v is affine in k). All FP32 quantities are small
+// offsets, which keeps coordinates accurate to a few 1e-6 pixel at 4096
+// pixels. Per voxel: v = v(kb) + t dv/dk, one truncation, one fraction.
+//
+// Tiled variant (the main path). Per view, the brick's detector footprint
+// is staged into LDS, transposed (v fastest, odd column pitch), as entries
+// holding q(u, v) and q(u+1, v) - q(u, v) for the row and for its mirror
+// row G - v, mirror rows in reverse order. A voxel and its mirror then read
+// the same two adjacent entries with the same weights: one address and one
+// fraction serve the pair, and the u-interpolation is a single FMA on the
+// staged difference. Staging uses buffer loads whose out-of-range offsets
+// return zero (taps outside the detector), and the next views' loads are
+// issued before the current views are computed.
+//
+// Direct variant (fallback when a tile exceeds the LDS budget, and the
+// reference the tiled variant is tested against bit for bit): identical
+// arithmetic, taps read from global memory.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,10 +42,10 @@
 namespace fdk {
 namespace {
 
-constexpr int kThreads = kBrickX * kBrickY;
-constexpr int kBlockX = 64;  // direct kernels: 64 x 4 columns per workgroup
-constexpr int kBlockY = 4;
-constexpr int kZT = 8;
+constexpr int kThreads = kBrickThreads;
+constexpr uint32_t kBadCol = 0x40000000u;  // pushes a buffer offset out of range
+constexpr uint32_t kBadRow = 0x80000000u;
+constexpr int kBufferWord3 = 0x00020000;   // raw buffer descriptor, gfx9 family
 
 template <typename T>
 __device__ __forceinline__ float tap(const T* __restrict__ qs, int32_t nu, int32_t nv, int32_t a,
@@ -45,32 +57,96 @@ __device__ __forceinline__ float tap(const T* __restrict__ qs, int32_t nu, int32
              : 0.0f;
 }
 
-// ------------------------------------------------------------------------
-// Tiled back-projection.
-// ------------------------------------------------------------------------
-
-// u and v(k) of column (i, j) in view g, FP64 (Eq. 2 in the Alg. 4 form).
-__device__ __forceinline__ void column_uv(const GeoConst& gc, const ViewGeo& g, int32_t i,
-                                          int32_t j, int32_t k, double* u, double* v,
-                                          double* f) {
-  const double di = static_cast<double>(i), dj = static_cast<double>(j);
-  const double z = fma(g.ci, di, fma(g.cj, dj, g.c0));
-  *f = 1.0 / z;
-  const double a = fma(g.ai, di, fma(g.aj, dj, g.a0));
-  *u = fma(gc.ku * a, *f, gc.cu);
-  *v = fma(gc.kv * (static_cast<double>(k) - gc.cz), *f, gc.cv);
+template <typename T>
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return to_f32(f16_t{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)});
+}
+template <>
+__device__ __forceinline__ float buf_load<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return to_f32(bf16_t{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)});
 }
 
-template <typename T, bool MIRROR>
-__global__ __launch_bounds__(kThreads) void bp_tiled_kernel(GeoConst gc, SliceRun run,
-                                                            ViewBatch vb, TileShape ts,
-                                                            const T* __restrict__ q,
-                                                            int64_t vstride,
-                                                            float* __restrict__ vol, float scale,
-                                                            int accumulate) {
-  extern __shared__ float4 tile[];
-  __shared__ int32_t org_u[kMaxViewsPerLaunch];
-  __shared__ int32_t org_v[kMaxViewsPerLaunch];
+// Per (brick, view) constants. With tx = i - i_lo, ty = j - j_lo and
+// dz = ci tx + cj ty, f = 1 / (zo + dz):
+//   u    - org_u = uo + (au tx + bu ty) f
+//   v(kb) - org_v = vo + (av tx + bv ty) f
+// (from u = cu + ku a / z and v = cv + kv (k - cz) / z, expanded about the
+// brick origin column so every FP32 term is a small offset).
+struct BrickView {
+  float uo, vo, au, bu, av, bv, zo, ci, cj;
+  int32_t org_u, org_v, pad;
+};
+
+__device__ BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i_lo, int32_t i_hi,
+                                 int32_t j_lo, int32_t j_hi, int32_t kb) {
+  const double k0 = static_cast<double>(kb) - gc.cz;
+  const double k1 = static_cast<double>(kb + kBrickZ - 1) - gc.cz;
+  // u is a ratio of functions affine in (i, j) and v is affine in k at
+  // fixed f: over the brick's (i, j, k) box both are extremal at corners.
+  double umin = INFINITY, vmin = INFINITY;
+  for (int c = 0; c < 4; ++c) {
+    const double di = (c & 1) ? i_hi : i_lo, dj = (c & 2) ? j_hi : j_lo;
+    const double z = fma(g.ci, di, fma(g.cj, dj, g.c0));
+    const double f = 1.0 / z;
+    const double a = fma(g.ai, di, fma(g.aj, dj, g.a0));
+    umin = fmin(umin, fma(gc.ku * a, f, gc.cu));
+    vmin = fmin(vmin, fmin(fma(gc.kv * k0, f, gc.cv), fma(gc.kv * k1, f, gc.cv)));
+  }
+  BrickView b;
+  b.org_u = static_cast<int32_t>(floor(umin)) - 1;
+  b.org_v = static_cast<int32_t>(floor(vmin)) - 1;
+  const double zo = fma(g.ci, static_cast<double>(i_lo), fma(g.cj, static_cast<double>(j_lo), g.c0));
+  const double fo = 1.0 / zo;
+  const double ao = fma(g.ai, static_cast<double>(i_lo), fma(g.aj, static_cast<double>(j_lo), g.a0));
+  const double ro = ao * fo;                 // a / z at the brick origin
+  const double K = gc.kv * k0;               // v(kb) - cv = K f
+  b.uo = static_cast<float>((gc.cu - b.org_u) + gc.ku * ro);
+  b.vo = static_cast<float>((gc.cv - b.org_v) + K * fo);
+  b.au = static_cast<float>(gc.ku * (g.ai - ro * g.ci));
+  b.bu = static_cast<float>(gc.ku * (g.aj - ro * g.cj));
+  b.av = static_cast<float>(-K * fo * g.ci);
+  b.bv = static_cast<float>(-K * fo * g.cj);
+  b.zo = static_cast<float>(zo);
+  b.ci = static_cast<float>(g.ci);
+  b.cj = static_cast<float>(g.cj);
+  b.pad = 0;
+  return b;
+}
+
+// FP32 column quantities of one view for a thread at (tx, ty) in the brick.
+struct ColumnF32 {
+  uint32_t nu, nvb;  // tile column and first row (relative to the origin)
+  float du, fvb;     // fractions of u and of v(kb)
+  float w, dvk;      // W_dis = f^2 and dv/dk
+};
+
+__device__ __forceinline__ ColumnF32 column_f32(const BrickView& b, float txf, float tyf,
+                                                float kvf) {
+  const float f = __builtin_amdgcn_rcpf(b.zo + fmaf(b.ci, txf, b.cj * tyf));
+  const float ul = fmaf(fmaf(b.au, txf, b.bu * tyf), f, b.uo);
+  const float vl = fmaf(fmaf(b.av, txf, b.bv * tyf), f, b.vo);
+  ColumnF32 c;
+  c.nu = static_cast<uint32_t>(ul);  // ul, vl >= 1 by the origin margin
+  c.du = __builtin_amdgcn_fractf(ul);
+  c.nvb = static_cast<uint32_t>(vl);
+  c.fvb = __builtin_amdgcn_fractf(vl);
+  c.w = f * f;
+  c.dvk = kvf * f;
+  return c;
+}
+
+template <typename T, bool MIRROR, bool TILED>
+__device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun& run,
+                                              const ViewBatch& vb, const TileShape& ts,
+                                              const T* __restrict__ q, int64_t vstride,
+                                              float* __restrict__ vol, float scale,
+                                              int accumulate, float4* tile, BrickView* bvs) {
 
   const int32_t tid = threadIdx.x;
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
@@ -86,104 +162,163 @@ __global__ __launch_bounds__(kThreads) void bp_tiled_kernel(GeoConst gc, SliceRu
   const int32_t i_lo = bx * kBrickX, j_lo = by * kBrickY;
   const int32_t i_hi = min(i_lo + kBrickX - 1, gc.nx - 1);
   const int32_t j_hi = min(j_lo + kBrickY - 1, gc.ny - 1);
-  const int32_t tx = tid % kBrickX, ty = tid / kBrickX;
-  const bool owner = (i_lo + tx <= i_hi) && (j_lo + ty <= j_hi);
-  const int32_t i = min(i_lo + tx, i_hi), j = min(j_lo + ty, j_hi);
+  const int32_t tx0 = tid % kBrickX, ty0 = tid / kBrickX;
+  const bool owner = (i_lo + tx0 <= i_hi) && (j_lo + ty0 <= j_hi);
+  const int32_t i = min(i_lo + tx0, i_hi), j = min(j_lo + ty0, j_hi);
+  const float txf = static_cast<float>(i - i_lo), tyf = static_cast<float>(j - j_lo);
   const int32_t t0 = seg * kBrickZ;
   const int32_t kb = run.k_first + t0;
+  const float kvf = static_cast<float>(gc.kv);
 
-  // Tile origin per view: u and v are extremal at the corners of the
-  // brick's (i, j, k) box (z is affine in i, j; u is a ratio of affine
-  // functions; v is affine in k at fixed f), so 8 corner evaluations bound
-  // every tap; one pixel of margin absorbs rounding.
-  if (tid < vb.nviews * 8) {
-    const int32_t s = tid >> 3, c = tid & 7;
-    double u, v, f;
-    column_uv(gc, vb.view[s], (c & 1) ? i_hi : i_lo, (c & 2) ? j_hi : j_lo,
-              (c & 4) ? kb + kBrickZ - 1 : kb, &u, &v, &f);
-#pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
-      u = fmin(u, __shfl_xor(u, m, 8));
-      v = fmin(v, __shfl_xor(v, m, 8));
-    }
-    if (c == 0) {
-      org_u[s] = static_cast<int32_t>(floor(u)) - 1;
-      org_v[s] = static_cast<int32_t>(floor(v)) - 1;
-    }
-  }
+  if (tid < vb.nviews) bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb);
   __syncthreads();
 
   float acc[kBrickZ], accm[kBrickZ];
 #pragma unroll
   for (int t = 0; t < kBrickZ; ++t) acc[t] = accm[t] = 0.0f;
 
-  const int32_t tu = ts.tu, tv = ts.tv, tuv = ts.tu * ts.tv;
-  const uint32_t row_bytes = static_cast<uint32_t>(tu) * kTileEntryBytes;
-  const char* tile_bytes = reinterpret_cast<const char*>(tile);
-  // Staging assignment, fixed for the kernel: thread -> tile column sc and
-  // first row sr; rows advance by rstep (threads beyond rstep * tu idle).
-  const int32_t rstep = kThreads / tu;
-  const int32_t sr = tid / tu, sc = tid - sr * tu;
-  const bool stager = sr < rstep;
-  for (int32_t s0 = 0; s0 < vb.nviews; s0 += ts.vc) {
-    const int32_t nvc = min(ts.vc, vb.nviews - s0);
-    if (s0 > 0) __syncthreads();  // the previous views' tiles are consumed
-    // Stage: entry (r, c) of view slot sl holds pixel (org_u + c, org_v + r)
-    // and its u-difference; for mirrored runs also pixel (org_u + c,
-    // G - org_v - r), the mirror row in reverse order.
-    if (stager) {
-      for (int32_t sl = 0; sl < nvc; ++sl) {
-        const int32_t s = s0 + sl;
-        const T* qs = q + s * vstride;
-        const int32_t gu = org_u[s] + sc;
-        float4* trow = tile + sl * tuv + sc;
-        for (int32_t r = sr; r < tv; r += rstep) {
-          const int32_t gr = org_v[s] + r;
-          float4 ent;
-          const float a0 = tap(qs, gc.nu, gc.nv, gu, gr), a1 = tap(qs, gc.nu, gc.nv, gu + 1, gr);
-          ent.x = a0;
-          ent.y = a1 - a0;
-          if (MIRROR) {
-            const int32_t gm = gc.mirror_g - gr;
-            const float b0 = tap(qs, gc.nu, gc.nv, gu, gm), b1 = tap(qs, gc.nu, gc.nv, gu + 1, gm);
-            ent.z = b0;
-            ent.w = b1 - b0;
-          } else {
-            ent.z = ent.w = 0.0f;
+  if constexpr (TILED) {
+    const int32_t tu = ts.tu, tv = ts.tv, tvp = ts.tvp, rstep = ts.rstep, rows = ts.rows;
+    const int32_t slot_entries = tu * tvp;
+    // Staging assignment: thread -> tile column sc and rows sr + m * rstep
+    // (lanes along u, so global reads are coalesced).
+    const int32_t sr = tid / tu, sc = tid - sr * tu;
+    const bool stager = sr < rstep;
+    const uint32_t es = sizeof(T);
+    const uint32_t row_es = static_cast<uint32_t>(gc.nu) * es;
+    const uint32_t nrec = static_cast<uint32_t>(gc.nu) * static_cast<uint32_t>(gc.nv) * es;
+    float4 pre[kPrefetchSlots];
+
+    // Issue the loads of views [s0, s0 + nvc) into pre[]: raw (q(u), q(u+1))
+    // for the row and for its mirror row.
+    auto load_stage = [&](int32_t s0, int32_t nvc) {
+      int32_t sl = 0, rr = 0;
+#pragma unroll
+      for (int m = 0; m < kPrefetchSlots; ++m) {
+        if (sl < nvc) {
+          const int32_t r = sr + rr * rstep;
+          if (stager && r < tv) {
+            const int32_t s = s0 + sl;
+            const __amdgpu_buffer_rsrc_t rsrc =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(q + s * vstride), 0, nrec,
+                                                  kBufferWord3);
+            const int32_t gu = bvs[s].org_u + sc;
+            const uint32_t c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
+                                    ? static_cast<uint32_t>(gu) * es : kBadCol;
+            const uint32_t c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
+                                    ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
+            const int32_t gr = bvs[s].org_v + r;
+            const uint32_t ro = static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
+                                    ? __umul24(static_cast<uint32_t>(gr), row_es) : kBadRow;
+            float4 p;
+            p.x = buf_load<T>(rsrc, ro + c0);
+            p.y = buf_load<T>(rsrc, ro + c1);
+            if (MIRROR) {
+              const int32_t gm = gc.mirror_g - gr;
+              const uint32_t rm = static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
+                                      ? __umul24(static_cast<uint32_t>(gm), row_es) : kBadRow;
+              p.z = buf_load<T>(rsrc, rm + c0);
+              p.w = buf_load<T>(rsrc, rm + c1);
+            } else {
+              p.z = p.w = 0.0f;
+            }
+            pre[m] = p;
           }
-          trow[r * tu] = ent;
+        }
+        if (++rr == rows) {
+          rr = 0;
+          ++sl;
+        }
+      }
+    };
+    // Write pre[] as tile entries: entry (r, c) of slot sl at
+    // sl * tu * tvp + c * tvp + r.
+    auto store_stage = [&](int32_t nvc) {
+      int32_t sl = 0, rr = 0;
+#pragma unroll
+      for (int m = 0; m < kPrefetchSlots; ++m) {
+        if (sl < nvc) {
+          const int32_t r = sr + rr * rstep;
+          if (stager && r < tv) {
+            const float4 p = pre[m];
+            tile[sl * slot_entries + sc * tvp + r] = make_float4(p.x, p.y - p.x, p.z, p.w - p.z);
+          }
+        }
+        if (++rr == rows) {
+          rr = 0;
+          ++sl;
+        }
+      }
+    };
+
+    const char* tile_bytes = reinterpret_cast<const char*>(tile);
+    load_stage(0, min(ts.vc, vb.nviews));
+    for (int32_t s0 = 0; s0 < vb.nviews; s0 += ts.vc) {
+      const int32_t nvc = min(ts.vc, vb.nviews - s0);
+      if (s0 > 0) __syncthreads();  // the previous views' tiles are consumed
+      store_stage(nvc);
+      __syncthreads();
+      if (s0 + ts.vc < vb.nviews) load_stage(s0 + ts.vc, min(ts.vc, vb.nviews - s0 - ts.vc));
+      for (int32_t sl = 0; sl < nvc; ++sl) {
+        const ColumnF32 c = column_f32(bvs[s0 + sl], txf, tyf, kvf);
+        const uint32_t nu = min(c.nu, static_cast<uint32_t>(tu - 1));
+        const uint32_t base =
+            static_cast<uint32_t>(sl * slot_entries) + nu * static_cast<uint32_t>(tvp) + c.nvb;
+        const char* pb = tile_bytes + base * kTileEntryBytes;
+        // Reads run one voxel pair ahead of use, so LDS latency overlaps the
+        // previous pair's arithmetic.
+        uint32_t dn;
+        float fr;
+        voxel_row_off(c.fvb, c.dvk, 0, &dn, &fr);
+        float4 A = reinterpret_cast<const float4*>(pb + dn * kTileEntryBytes)[0];
+        float4 B = reinterpret_cast<const float4*>(pb + dn * kTileEntryBytes)[1];
+#pragma unroll
+        for (int t = 0; t < kBrickZ; ++t) {
+          float4 An = A, Bn = B;
+          uint32_t dn1 = 0;
+          float fr1 = 0.0f;
+          if (t + 1 < kBrickZ) {
+            voxel_row_off(c.fvb, c.dvk, t + 1, &dn1, &fr1);
+            const float4* p = reinterpret_cast<const float4*>(pb + dn1 * kTileEntryBytes);
+            An = p[0];
+            Bn = p[1];
+          }
+          const float ta = fmaf(c.du, A.y, A.x), tb = fmaf(c.du, B.y, B.x);
+          acc[t] = fmaf(c.w, fmaf(fr, tb - ta, ta), acc[t]);
+          if (MIRROR) {
+            const float ma = fmaf(c.du, A.w, A.z), mb = fmaf(c.du, B.w, B.z);
+            accm[t] = fmaf(c.w, fmaf(fr, mb - ma, ma), accm[t]);
+          }
+          A = An;
+          B = Bn;
+          fr = fr1;
         }
       }
     }
-    __syncthreads();
-
-    for (int32_t sl = 0; sl < nvc; ++sl) {
-      const int32_t s = s0 + sl;
-      double u, v, f;
-      column_uv(gc, vb.view[s], i, j, kb, &u, &v, &f);
-      const double ul = u - org_u[s], vl = v - org_v[s];  // exact: integer shifts
-      const double fu = floor(ul), fv = floor(vl);
-      const int32_t nu = static_cast<int32_t>(fu), nvb = static_cast<int32_t>(fv);
-      const float du = static_cast<float>(ul - fu);
-      const float fvb = static_cast<float>(vl - fv);
-      const float w = static_cast<float>(f * f);
-      const float dvk = static_cast<float>(gc.kv * f);
-      // LDS byte offsets: entry (row, col) of slot sl at
-      // ((sl * tv + row) * tu + col) * 16; rows advance by row_bytes.
-      const uint32_t base = (static_cast<uint32_t>(sl * tuv + nvb * tu + nu)) * kTileEntryBytes;
+  } else {
+    for (int32_t s = 0; s < vb.nviews; ++s) {
+      const ColumnF32 c = column_f32(bvs[s], txf, tyf, kvf);
+      const T* qs = q + s * vstride;
+      const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
+      const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);
 #pragma unroll
       for (int t = 0; t < kBrickZ; ++t) {
         uint32_t dn;
         float fr;
-        voxel_row_off(fvb, dvk, t, &dn, &fr);
-        const uint32_t off = __umul24(dn, row_bytes) + base;
-        const float4 A = *reinterpret_cast<const float4*>(tile_bytes + off);
-        const float4 B = *reinterpret_cast<const float4*>(tile_bytes + off + row_bytes);
-        const float ta = fmaf(du, A.y, A.x), tb = fmaf(du, B.y, B.x);
-        acc[t] = fmaf(w, fmaf(fr, tb - ta, ta), acc[t]);
+        voxel_row_off(c.fvb, c.dvk, t, &dn, &fr);
+        const int32_t n = nb + static_cast<int32_t>(dn);
+        const float q0a = tap(qs, gc.nu, gc.nv, a, n), q1a = tap(qs, gc.nu, gc.nv, a + 1, n);
+        const float q0b = tap(qs, gc.nu, gc.nv, a, n + 1), q1b = tap(qs, gc.nu, gc.nv, a + 1, n + 1);
+        const float ta = fmaf(c.du, q1a - q0a, q0a), tb = fmaf(c.du, q1b - q0b, q0b);
+        acc[t] = fmaf(c.w, fmaf(fr, tb - ta, ta), acc[t]);
         if (MIRROR) {
-          const float ma = fmaf(du, A.w, A.z), mb = fmaf(du, B.w, B.z);
-          accm[t] = fmaf(w, fmaf(fr, mb - ma, ma), accm[t]);
+          // Theorem 1: v(Nz-1-k) = G - v(k): rows G - n (weight 1 - fr) and
+          // G - n - 1 (weight fr).
+          const int32_t m = gc.mirror_g - n;
+          const float r0a = tap(qs, gc.nu, gc.nv, a, m), r1a = tap(qs, gc.nu, gc.nv, a + 1, m);
+          const float r0b = tap(qs, gc.nu, gc.nv, a, m - 1), r1b = tap(qs, gc.nu, gc.nv, a + 1, m - 1);
+          const float ma = fmaf(c.du, r1a - r0a, r0a), mb = fmaf(c.du, r1b - r0b, r0b);
+          accm[t] = fmaf(c.w, fmaf(fr, mb - ma, ma), accm[t]);
         }
       }
     }
@@ -204,71 +339,37 @@ __global__ __launch_bounds__(kThreads) void bp_tiled_kernel(GeoConst gc, SliceRu
   }
 }
 
-// ------------------------------------------------------------------------
-// Direct back-projection (fallback) and the adjoint.
-// ------------------------------------------------------------------------
-
-// Alg. 3 on rows ra (weight 1 - fr) and rb (weight fr), columns a, a + 1.
-template <typename T>
-__device__ __forceinline__ float bilinear(const T* __restrict__ qs, int32_t nu, int32_t nv,
-                                          int32_t a, float du, int32_t ra, int32_t rb, float fr) {
-  const float q0a = tap(qs, nu, nv, a, ra), q1a = tap(qs, nu, nv, a + 1, ra);
-  const float q0b = tap(qs, nu, nv, a, rb), q1b = tap(qs, nu, nv, a + 1, rb);
-  const float ta = fmaf(du, q1a - q0a, q0a);
-  const float tb = fmaf(du, q1b - q0b, q0b);
-  return fmaf(fr, tb - ta, ta);
+// Occupancy of the tiled variant is set by LDS (three 256-thread
+// workgroups per CU, three waves per SIMD), which leaves up to 168 VGPRs
+// per lane for the prefetched tile entries.
+template <typename T, bool MIRROR>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void bp_tiled_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                     const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
+                     float scale, int accumulate) {
+  extern __shared__ float4 tile[];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  bp_brick_body<T, MIRROR, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
 }
 
 template <typename T, bool MIRROR>
-__global__ __launch_bounds__(kBlockX* kBlockY) void bp_direct_kernel(GeoConst gc, SliceRun run,
-                                                                     ViewBatch vb,
-                                                                     const T* __restrict__ q,
-                                                                     int64_t vstride,
-                                                                     float* __restrict__ vol,
-                                                                     float scale, int accumulate) {
-  const int32_t i = blockIdx.x * kBlockX + threadIdx.x;
-  const int32_t j = blockIdx.y * kBlockY + threadIdx.y;
-  const int32_t t0 = blockIdx.z * kZT;
-  if (i >= gc.nx || j >= gc.ny) return;
-  const int32_t kb = run.k_first + t0;
-  float acc[kZT], accm[kZT];
-#pragma unroll
-  for (int t = 0; t < kZT; ++t) acc[t] = accm[t] = 0.0f;
-
-  for (int32_t s = 0; s < vb.nviews; ++s) {
-    const ColumnView c = column_view(gc, vb.view[s], i, j, kb);
-    const T* qs = q + s * vstride;
-#pragma unroll
-    for (int t = 0; t < kZT; ++t) {
-      int32_t n;
-      float fr;
-      voxel_row(c, t, &n, &fr);
-      acc[t] = fmaf(c.w, bilinear(qs, gc.nu, gc.nv, c.nu0, c.du, n, n + 1, fr), acc[t]);
-      if (MIRROR) {
-        // Theorem 1: v(Nz-1-k) = G - v(k), so the mirror voxel samples rows
-        // G - n (weight 1 - fr) and G - 1 - n (weight fr).
-        const int32_t m = gc.mirror_g - n;
-        accm[t] = fmaf(c.w, bilinear(qs, gc.nu, gc.nv, c.nu0, c.du, m, m - 1, fr), accm[t]);
-      }
-    }
-  }
-
-  const int64_t slice = static_cast<int64_t>(gc.nx) * gc.ny;
-  const int64_t col = static_cast<int64_t>(j) * gc.nx + i;
-#pragma unroll
-  for (int t = 0; t < kZT; ++t) {
-    if (t0 + t >= run.n) break;
-    float* p = vol + static_cast<int64_t>(run.loc_lo + t0 + t) * slice + col;
-    *p = accumulate ? fmaf(scale, acc[t], *p) : scale * acc[t];
-    if (MIRROR) {
-      float* pm = vol + static_cast<int64_t>(run.loc_hi - t0 - t) * slice + col;
-      *pm = accumulate ? fmaf(scale, accm[t], *pm) : scale * accm[t];
-    }
-  }
+__global__ __launch_bounds__(kThreads) void bp_direct_kernel(GeoConst gc, SliceRun run,
+                                                             ViewBatch vb, TileShape ts,
+                                                             const T* __restrict__ q,
+                                                             int64_t vstride,
+                                                             float* __restrict__ vol, float scale,
+                                                             int accumulate) {
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  bp_brick_body<T, MIRROR, false>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, nullptr,
+                                  bvs);
 }
 
-// Adjoint: every voxel scatters scale * W * w_tap * vol into its taps with
-// the coordinates and weights the back-projectors sample with.
+// ------------------------------------------------------------------------
+// Adjoint (forward projection): every voxel scatters scale * W * w_tap * vol
+// into its taps with exactly the coordinates and weights bp_brick_body
+// samples with (same brick setup, same FP32 column arithmetic).
+// ------------------------------------------------------------------------
+
 __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_t nv, int32_t a,
                                       float du, int32_t ra, int32_t rb, float fr, float val) {
   const float wa = val * (1.0f - fr), wb = val * fr;
@@ -284,39 +385,59 @@ __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_
 }
 
 template <bool MIRROR>
-__global__ __launch_bounds__(kBlockX* kBlockY) void fp_kernel(GeoConst gc, SliceRun run,
-                                                              ViewBatch vb,
-                                                              const float* __restrict__ vol,
-                                                              float* __restrict__ q,
-                                                              int64_t vstride, float scale) {
-  const int32_t i = blockIdx.x * kBlockX + threadIdx.x;
-  const int32_t j = blockIdx.y * kBlockY + threadIdx.y;
-  const int32_t t0 = blockIdx.z * kZT;
-  if (i >= gc.nx || j >= gc.ny) return;
+__global__ __launch_bounds__(kThreads) void fp_brick_kernel(GeoConst gc, SliceRun run,
+                                                            ViewBatch vb, TileShape ts,
+                                                            const float* __restrict__ vol,
+                                                            float* __restrict__ q,
+                                                            int64_t vstride, float scale) {
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  const int32_t tid = threadIdx.x;
+  uint32_t lin = blockIdx.x;
+  const int32_t bx = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nbx));
+  lin /= static_cast<uint32_t>(ts.nbx);
+  const int32_t by = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nby));
+  const int32_t seg = static_cast<int32_t>(lin / static_cast<uint32_t>(ts.nby));
+  const int32_t i_lo = bx * kBrickX, j_lo = by * kBrickY;
+  const int32_t i_hi = min(i_lo + kBrickX - 1, gc.nx - 1);
+  const int32_t j_hi = min(j_lo + kBrickY - 1, gc.ny - 1);
+  const int32_t tx0 = tid % kBrickX, ty0 = tid / kBrickX;
+  const bool owner = (i_lo + tx0 <= i_hi) && (j_lo + ty0 <= j_hi);
+  const int32_t i = min(i_lo + tx0, i_hi), j = min(j_lo + ty0, j_hi);
+  const float txf = static_cast<float>(i - i_lo), tyf = static_cast<float>(j - j_lo);
+  const int32_t t0 = seg * kBrickZ;
   const int32_t kb = run.k_first + t0;
+  const float kvf = static_cast<float>(gc.kv);
+
+  if (tid < vb.nviews) bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb);
+  __syncthreads();
+  if (!owner) return;
+
   const int64_t slice = static_cast<int64_t>(gc.nx) * gc.ny;
   const int64_t col = static_cast<int64_t>(j) * gc.nx + i;
-  float x[kZT], xm[kZT];
+  float x[kBrickZ], xm[kBrickZ];
 #pragma unroll
-  for (int t = 0; t < kZT; ++t) {
+  for (int t = 0; t < kBrickZ; ++t) {
     const bool in = t0 + t < run.n;
     x[t] = in ? scale * vol[static_cast<int64_t>(run.loc_lo + t0 + t) * slice + col] : 0.0f;
     xm[t] = (MIRROR && in) ? scale * vol[static_cast<int64_t>(run.loc_hi - t0 - t) * slice + col]
                            : 0.0f;
   }
   for (int32_t s = 0; s < vb.nviews; ++s) {
-    const ColumnView c = column_view(gc, vb.view[s], i, j, kb);
+    const ColumnF32 c = column_f32(bvs[s], txf, tyf, kvf);
     float* qs = q + s * vstride;
+    const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
+    const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);
 #pragma unroll
-    for (int t = 0; t < kZT; ++t) {
+    for (int t = 0; t < kBrickZ; ++t) {
       if (t0 + t >= run.n) break;
-      int32_t n;
+      uint32_t dn;
       float fr;
-      voxel_row(c, t, &n, &fr);
-      splat(qs, gc.nu, gc.nv, c.nu0, c.du, n, n + 1, fr, c.w * x[t]);
+      voxel_row_off(c.fvb, c.dvk, t, &dn, &fr);
+      const int32_t n = nb + static_cast<int32_t>(dn);
+      splat(qs, gc.nu, gc.nv, a, c.du, n, n + 1, fr, c.w * x[t]);
       if (MIRROR) {
         const int32_t m = gc.mirror_g - n;
-        splat(qs, gc.nu, gc.nv, c.nu0, c.du, m, m - 1, fr, c.w * xm[t]);
+        splat(qs, gc.nu, gc.nv, a, c.du, m, m - 1, fr, c.w * xm[t]);
       }
     }
   }
@@ -328,36 +449,29 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t n) {
     p[m] = 0.0f;
 }
 
-dim3 column_grid(const GeoConst& gc, const SliceRun& run) {
-  return dim3((gc.nx + kBlockX - 1) / kBlockX, (gc.ny + kBlockY - 1) / kBlockY,
-              (run.n + kZT - 1) / kZT);
-}
-
 template <typename T>
 int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, const TileShape& ts,
                 const void* q, int64_t vstride, float* vol, float scale, int accumulate,
                 hipStream_t st) {
   const T* qt = static_cast<const T*>(q);
+  const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
+  const dim3 grid(static_cast<uint32_t>(nwg)), block(kThreads);
   if (ts.vc > 0) {
-    const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
-    const size_t lds = static_cast<size_t>(ts.vc) * ts.tu * ts.tv * kTileEntryBytes;
+    const size_t lds = static_cast<size_t>(ts.vc) * ts.tu * ts.tvp * kTileEntryBytes;
     if (run.mirror)
-      hipLaunchKernelGGL((bp_tiled_kernel<T, true>), dim3(static_cast<uint32_t>(nwg)),
-                         dim3(kThreads), lds, st, gc, run, vb, ts, qt, vstride, vol, scale,
-                         accumulate);
+      hipLaunchKernelGGL((bp_tiled_kernel<T, true>), grid, block, lds, st, gc, run, vb, ts,
+                         qt, vstride, vol, scale, accumulate);
     else
-      hipLaunchKernelGGL((bp_tiled_kernel<T, false>), dim3(static_cast<uint32_t>(nwg)),
-                         dim3(kThreads), lds, st, gc, run, vb, ts, qt, vstride, vol, scale,
-                         accumulate);
-    return static_cast<int>(hipGetLastError());
+      hipLaunchKernelGGL((bp_tiled_kernel<T, false>), grid, block, lds, st, gc, run, vb, ts,
+                         qt, vstride, vol, scale, accumulate);
+  } else {
+    if (run.mirror)
+      hipLaunchKernelGGL((bp_direct_kernel<T, true>), grid, block, 0, st, gc, run, vb, ts,
+                         qt, vstride, vol, scale, accumulate);
+    else
+      hipLaunchKernelGGL((bp_direct_kernel<T, false>), grid, block, 0, st, gc, run, vb, ts,
+                         qt, vstride, vol, scale, accumulate);
   }
-  const dim3 grid = column_grid(gc, run), block(kBlockX, kBlockY);
-  if (run.mirror)
-    hipLaunchKernelGGL((bp_direct_kernel<T, true>), grid, block, 0, st, gc, run, vb, qt, vstride,
-                       vol, scale, accumulate);
-  else
-    hipLaunchKernelGGL((bp_direct_kernel<T, false>), grid, block, 0, st, gc, run, vb, qt,
-                       vstride, vol, scale, accumulate);
   return static_cast<int>(hipGetLastError());
 }
 
@@ -377,7 +491,7 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   ts.nby = (gc.ny + kBrickY - 1) / kBrickY;
   ts.nseg = (run.n + kBrickZ - 1) / kBrickZ;
   const char* env = std::getenv("FDK_BP_KERNEL");
-  if (env && std::strcmp(env, "direct") == 0) return ts;  // vc = 0: direct kernel
+  if (env && std::strcmp(env, "direct") == 0) return ts;  // vc = 0: direct variant
   const double r = 0.5 * std::hypot((g->nx - 1) * g->dx, (g->ny - 1) * g->dy);
   const double zmin = g->sod - r, rho = r / zmin;
   const double kmax = gc.cz + kBrickZ;
@@ -392,12 +506,18 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
     wv = std::fmax(wv, gc.kv * ((kBrickZ - 1) / zmin + kmax * dz / (zmin * zmin)));
   }
   // floor() of the extremes adds one pixel, the second tap one row, the
-  // origin margin one pixel, and one more absorbs rounding.
-  ts.tu = static_cast<int32_t>(std::ceil(wu)) + 3;
-  ts.tv = static_cast<int32_t>(std::ceil(wv)) + 4;
-  const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tv * kTileEntryBytes;
-  ts.vc = static_cast<int32_t>(std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view));
-  if (ts.tu > kThreads) ts.vc = 0;  // staging maps one thread per tile column
+  // origin margin one pixel, FP32 column arithmetic up to one more.
+  ts.tu = static_cast<int32_t>(std::ceil(wu)) + 4;
+  ts.tv = static_cast<int32_t>(std::ceil(wv)) + 5;
+  ts.tvp = ts.tv | 1;  // odd pitch: 16 neighbouring columns hit distinct LDS banks
+  if (ts.tu > kThreads) return ts;
+  ts.rstep = kThreads / ts.tu;
+  ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
+  const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * kTileEntryBytes;
+  int64_t vc = std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);
+  vc = std::min<int64_t>(vc, kPrefetchSlots / ts.rows);
+  if (const char* cap = std::getenv("FDK_BP_VC")) vc = std::min<int64_t>(vc, std::atoi(cap));
+  ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
   return ts;
 }
 
@@ -417,15 +537,16 @@ int launch_backproject(const GeoConst& gc, const SliceRun& run, const ViewBatch&
 }
 
 int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
-                           const float* vol, float* q, int64_t vstride, float scale,
-                           void* stream) {
+                           const TileShape& ts, const float* vol, float* q, int64_t vstride,
+                           float scale, void* stream) {
+  const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const dim3 grid = column_grid(gc, run), block(kBlockX, kBlockY);
   if (run.mirror)
-    hipLaunchKernelGGL((fp_kernel<true>), grid, block, 0, st, gc, run, vb, vol, q, vstride, scale);
+    hipLaunchKernelGGL((fp_brick_kernel<true>), dim3(static_cast<uint32_t>(nwg)), dim3(kThreads), 0,
+                       st, gc, run, vb, ts, vol, q, vstride, scale);
   else
-    hipLaunchKernelGGL((fp_kernel<false>), grid, block, 0, st, gc, run, vb, vol, q, vstride,
-                       scale);
+    hipLaunchKernelGGL((fp_brick_kernel<false>), dim3(static_cast<uint32_t>(nwg)), dim3(kThreads), 0,
+                       st, gc, run, vb, ts, vol, q, vstride, scale);
   return static_cast<int>(hipGetLastError());
 }
 

@@ -42,7 +42,7 @@ fdk_status check_geometry(const fdk_geometry* g) {
                 g->ny, g->nz);
   if (g->nu <= 0 || g->nv <= 0)
     return fail(FDK_ERR_INVALID_ARG, "detector size must be positive (got %d x %d)", g->nu, g->nv);
-  if ((int64_t)g->nu * g->nv > (int64_t)1 << 30)
+  if ((int64_t)g->nu * g->nv > (int64_t)1 << 27)
     return fail(FDK_ERR_INVALID_ARG, "detector of %d x %d pixels is too large", g->nu, g->nv);
   if ((int64_t)g->nx * g->ny > (int64_t)1 << 30)
     return fail(FDK_ERR_INVALID_ARG, "volume slice of %d x %d voxels is too large", g->nx, g->ny);
@@ -257,8 +257,9 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
     vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
     for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
     for (const fdk::SliceRun& r : sl.runs) {
-      if (int e = fdk::launch_forward_project(gc, r, vb, vol, q + (size_t)b * vstride, vstride,
-                                              scale, stream))
+      const fdk::TileShape ts = fdk::tile_shape(g, gc, r, vb);
+      if (int e = fdk::launch_forward_project(gc, r, vb, ts, vol, q + (size_t)b * vstride,
+                                              vstride, scale, stream))
         return fail(FDK_ERR_HIP, "forward-projection launch failed: HIP error %d", e);
     }
   }

@@ -45,25 +45,30 @@ struct ViewBatch {
   int32_t nviews;
 };
 
-// LDS-tiled back-projection: a workgroup owns a brick of kBrickX x kBrickY
-// columns and kBrickZ voxel pairs per column; per view it stages the
-// brick's detector footprint, a tile of tu x tv pixels, into LDS, vc views
-// at a time. tu and tv are host-side upper bounds of the footprint.
+// Bricked back-projection: a workgroup of 256 threads owns a brick of
+// kBrickX x kBrickY columns and kBrickZ consecutive slices of a slice run
+// (plus their mirrors for a mirrored run). In the tiled variant it stages
+// the brick's detector footprint for each view, a tile of tu x tv pixels,
+// into LDS, vc views at a time. tu and tv are host-side upper bounds.
 constexpr int kBrickX = 16;
 constexpr int kBrickY = 16;
 constexpr int kBrickZ = 16;
+constexpr int kBrickThreads = kBrickX * kBrickY;
 constexpr int kMaxStageViews = 4;
-constexpr int kTileLdsBytes = 61440;
-constexpr int kTileEntryBytes = 16;  // (q, dq/du) for a row and its mirror
+constexpr int kPrefetchSlots = 12;      // tile entries a thread prefetches per stage
+constexpr int kTileLdsBytes = 61440;    // LDS budget for the tiles of one stage
+constexpr int kTileEntryBytes = 16;     // (q, dq/du) of a row and of its mirror row
 
 struct TileShape {
-  int32_t tu, tv, vc;    // tile columns, rows, views staged at once (0: no tiling)
-  int32_t nbx, nby, nseg;  // bricks along x, y and z-segments in the run
+  int32_t tu, tv, tvp;   // tile columns, rows, and the (odd) column pitch in entries
+  int32_t vc;            // views staged at once; 0 selects the direct variant
+  int32_t rstep, rows;   // staging: rows advanced per pass, passes per view
+  int32_t nbx, nby, nseg;  // bricks along x, y and z-segments of the run
 };
 
-// Kernel choice for fdk_backproject: tiled unless the footprint tile does
-// not fit the LDS budget (or the FDK_BP_KERNEL environment variable asks
-// for "direct", a debugging aid).
+// Kernel choice for a run and view batch: tiled unless the footprint tile
+// exceeds the LDS or prefetch budget (or FDK_BP_KERNEL=direct, a debugging
+// aid; FDK_BP_VC caps the views per stage, a tuning aid).
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb);
 
@@ -73,8 +78,8 @@ int launch_backproject(const GeoConst& gc, const SliceRun& run, const ViewBatch&
                        int64_t view_stride, float* vol, float scale, int accumulate,
                        void* stream);
 int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
-                           const float* vol, float* q, int64_t view_stride, float scale,
-                           void* stream);
+                           const TileShape& ts, const float* vol, float* q, int64_t view_stride,
+                           float scale, void* stream);
 int launch_fill_zero(float* p, int64_t n, void* stream);
 int launch_filter(const GeoConst& gc, double du, double dv, double sod, double sdd,
                   int32_t nrows, const float* e, void* q, fdk_dtype out_dtype,
