@@ -141,6 +141,30 @@ __device__ __forceinline__ ColumnF32 column_f32(const BrickView& b, float txf, f
   return c;
 }
 
+// The same quantities computed per column in FP64 (direct variant: it runs
+// when footprints are too large for LDS, i.e. at strong magnification,
+// where brick-relative FP32 offsets would span hundreds of pixels).
+// Indices are relative to the brick's tile origin, as in column_f32.
+__device__ __forceinline__ ColumnF32 column_f64(const GeoConst& gc, const ViewGeo& g,
+                                                const BrickView& b, int32_t i, int32_t j,
+                                                int32_t kb) {
+  const double di = static_cast<double>(i), dj = static_cast<double>(j);
+  const double z = fma(g.ci, di, fma(g.cj, dj, g.c0));
+  const double f = 1.0 / z;
+  const double a = fma(g.ai, di, fma(g.aj, dj, g.a0));
+  const double ul = fma(gc.ku * a, f, gc.cu) - b.org_u;  // exact: integer shift
+  const double vl = fma(gc.kv * (static_cast<double>(kb) - gc.cz), f, gc.cv) - b.org_v;
+  const double fu = floor(ul), fv = floor(vl);
+  ColumnF32 c;
+  c.nu = static_cast<uint32_t>(fu);
+  c.du = static_cast<float>(ul - fu);
+  c.nvb = static_cast<uint32_t>(fv);
+  c.fvb = static_cast<float>(vl - fv);
+  c.w = static_cast<float>(f * f);
+  c.dvk = static_cast<float>(gc.kv * f);
+  return c;
+}
+
 template <typename T, bool MIRROR, bool TILED>
 __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun& run,
                                               const ViewBatch& vb, const TileShape& ts,
@@ -297,7 +321,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     }
   } else {
     for (int32_t s = 0; s < vb.nviews; ++s) {
-      const ColumnF32 c = column_f32(bvs[s], txf, tyf, kvf);
+      const ColumnF32 c = column_f64(gc, vb.view[s], bvs[s], i, j, kb);
       const T* qs = q + s * vstride;
       const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
       const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);
@@ -339,17 +363,29 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   }
 }
 
-// Occupancy of the tiled variant is set by LDS (three 256-thread
+// Occupancy of the mirrored tiled variant is set by LDS (three 256-thread
 // workgroups per CU, three waves per SIMD), which leaves up to 168 VGPRs
 // per lane for the prefetched tile entries.
-template <typename T, bool MIRROR>
+template <typename T>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
-void bp_tiled_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
-                     const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
-                     float scale, int accumulate) {
+void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                            const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
+                            float scale, int accumulate) {
   extern __shared__ float4 tile[];
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
-  bp_brick_body<T, MIRROR, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
+  bp_brick_body<T, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void bp_tiled_plain_kernel(GeoConst gc, SliceRun run,
+                                                                  ViewBatch vb, TileShape ts,
+                                                                  const T* __restrict__ q,
+                                                                  int64_t vstride,
+                                                                  float* __restrict__ vol,
+                                                                  float scale, int accumulate) {
+  extern __shared__ float4 tile[];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  bp_brick_body<T, false, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
 }
 
 template <typename T, bool MIRROR>
@@ -366,8 +402,16 @@ __global__ __launch_bounds__(kThreads) void bp_direct_kernel(GeoConst gc, SliceR
 
 // ------------------------------------------------------------------------
 // Adjoint (forward projection): every voxel scatters scale * W * w_tap * vol
-// into its taps with exactly the coordinates and weights bp_brick_body
-// samples with (same brick setup, same FP32 column arithmetic).
+// into its four taps, with exactly the coordinates and weights of the
+// matching back-projection variant (same brick setup; FP32 columns for the
+// tiled variant, FP64 columns for the direct one), so each is the transpose
+// of its back-projector up to rounding.
+//
+// Tiled variant: per view, the brick's splats accumulate in an LDS tile with
+// the back-projector's transposed layout (one more column, for the u + 1
+// taps), (main row, mirror row) pairs per entry, by LDS float atomics; the
+// tile is then added to the projection with one global atomic per non-zero
+// entry. Direct variant: global atomics per tap.
 // ------------------------------------------------------------------------
 
 __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_t nv, int32_t a,
@@ -384,52 +428,156 @@ __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_
   }
 }
 
-template <bool MIRROR>
-__global__ __launch_bounds__(kThreads) void fp_brick_kernel(GeoConst gc, SliceRun run,
-                                                            ViewBatch vb, TileShape ts,
-                                                            const float* __restrict__ vol,
-                                                            float* __restrict__ q,
-                                                            int64_t vstride, float scale) {
-  __shared__ BrickView bvs[kMaxViewsPerLaunch];
-  const int32_t tid = threadIdx.x;
+struct BrickCoords {
+  int32_t i_lo, i_hi, j_lo, j_hi, i, j, t0, kb;
+  float txf, tyf;
+  bool owner;
+};
+
+__device__ __forceinline__ BrickCoords brick_coords(const GeoConst& gc, const SliceRun& run,
+                                                    const TileShape& ts) {
+  const uint32_t nwg = gridDim.x;
   uint32_t lin = blockIdx.x;
+  if ((nwg & 7u) == 0) lin = (lin & 7u) * (nwg >> 3) + (lin >> 3);
   const int32_t bx = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nbx));
   lin /= static_cast<uint32_t>(ts.nbx);
   const int32_t by = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nby));
   const int32_t seg = static_cast<int32_t>(lin / static_cast<uint32_t>(ts.nby));
-  const int32_t i_lo = bx * kBrickX, j_lo = by * kBrickY;
-  const int32_t i_hi = min(i_lo + kBrickX - 1, gc.nx - 1);
-  const int32_t j_hi = min(j_lo + kBrickY - 1, gc.ny - 1);
-  const int32_t tx0 = tid % kBrickX, ty0 = tid / kBrickX;
-  const bool owner = (i_lo + tx0 <= i_hi) && (j_lo + ty0 <= j_hi);
-  const int32_t i = min(i_lo + tx0, i_hi), j = min(j_lo + ty0, j_hi);
-  const float txf = static_cast<float>(i - i_lo), tyf = static_cast<float>(j - j_lo);
-  const int32_t t0 = seg * kBrickZ;
-  const int32_t kb = run.k_first + t0;
-  const float kvf = static_cast<float>(gc.kv);
+  BrickCoords bc;
+  bc.i_lo = bx * kBrickX;
+  bc.j_lo = by * kBrickY;
+  bc.i_hi = min(bc.i_lo + kBrickX - 1, gc.nx - 1);
+  bc.j_hi = min(bc.j_lo + kBrickY - 1, gc.ny - 1);
+  const int32_t tx0 = threadIdx.x % kBrickX, ty0 = threadIdx.x / kBrickX;
+  bc.owner = (bc.i_lo + tx0 <= bc.i_hi) && (bc.j_lo + ty0 <= bc.j_hi);
+  bc.i = min(bc.i_lo + tx0, bc.i_hi);
+  bc.j = min(bc.j_lo + ty0, bc.j_hi);
+  bc.txf = static_cast<float>(bc.i - bc.i_lo);
+  bc.tyf = static_cast<float>(bc.j - bc.j_lo);
+  bc.t0 = seg * kBrickZ;
+  bc.kb = run.k_first + bc.t0;
+  return bc;
+}
 
-  if (tid < vb.nviews) bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb);
-  __syncthreads();
-  if (!owner) return;
-
+template <bool MIRROR>
+__device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& run,
+                                            const BrickCoords& bc, const float* __restrict__ vol,
+                                            float scale, float* x, float* xm) {
   const int64_t slice = static_cast<int64_t>(gc.nx) * gc.ny;
-  const int64_t col = static_cast<int64_t>(j) * gc.nx + i;
-  float x[kBrickZ], xm[kBrickZ];
+  const int64_t col = static_cast<int64_t>(bc.j) * gc.nx + bc.i;
 #pragma unroll
   for (int t = 0; t < kBrickZ; ++t) {
-    const bool in = t0 + t < run.n;
-    x[t] = in ? scale * vol[static_cast<int64_t>(run.loc_lo + t0 + t) * slice + col] : 0.0f;
-    xm[t] = (MIRROR && in) ? scale * vol[static_cast<int64_t>(run.loc_hi - t0 - t) * slice + col]
-                           : 0.0f;
+    const bool in = bc.owner && (bc.t0 + t < run.n);
+    x[t] = in ? scale * vol[static_cast<int64_t>(run.loc_lo + bc.t0 + t) * slice + col] : 0.0f;
+    xm[t] = (MIRROR && in)
+                ? scale * vol[static_cast<int64_t>(run.loc_hi - bc.t0 - t) * slice + col]
+                : 0.0f;
   }
+}
+
+template <bool MIRROR>
+__global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRun run,
+                                                            ViewBatch vb, TileShape ts,
+                                                            const float* __restrict__ vol,
+                                                            float* __restrict__ q,
+                                                            int64_t vstride, float scale) {
+  extern __shared__ float2 atile[];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  const int32_t tid = threadIdx.x;
+  const BrickCoords bc = brick_coords(gc, run, ts);
+  if (tid < vb.nviews)
+    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+  float x[kBrickZ], xm[kBrickZ];
+  load_voxels<MIRROR>(gc, run, bc, vol, scale, x, xm);
+  __syncthreads();
+
+  const float kvf = static_cast<float>(gc.kv);
+  const int32_t tuf = ts.tu + 1, tv = ts.tv, tvp = ts.tvp;
+  const int32_t slot = tuf * tvp;
+  const int32_t rstep = kThreads / tuf;
+  const int32_t sr = tid / tuf, sc = tid - sr * tuf;
+  for (int32_t s0 = 0; s0 < vb.nviews; s0 += ts.vc) {
+    const int32_t nvc = min(ts.vc, vb.nviews - s0);
+    for (int32_t e = tid; e < nvc * slot; e += kThreads) atile[e] = make_float2(0.0f, 0.0f);
+    __syncthreads();
+    if (bc.owner) {
+      for (int32_t sl = 0; sl < nvc; ++sl) {
+        const ColumnF32 c = column_f32(bvs[s0 + sl], bc.txf, bc.tyf, kvf);
+        const uint32_t nu = min(c.nu, static_cast<uint32_t>(ts.tu - 1));
+        float* base = reinterpret_cast<float*>(atile + sl * slot + nu * tvp + c.nvb);
+        const float du0 = 1.0f - c.du;
+#pragma unroll
+        for (int t = 0; t < kBrickZ; ++t) {
+          uint32_t dn;
+          float fr;
+          voxel_row_off(c.fvb, c.dvk, t, &dn, &fr);
+          float* e = base + 2 * dn;  // float2 entries: (main, mirror)
+          const float val = c.w * x[t];
+          const float wa = val - val * fr, wb = val * fr;
+          atomicAdd(e, wa * du0);
+          atomicAdd(e + 2 * tvp, wa * c.du);
+          atomicAdd(e + 2, wb * du0);
+          atomicAdd(e + 2 * tvp + 2, wb * c.du);
+          if (MIRROR) {
+            const float vm = c.w * xm[t];
+            const float ma = vm - vm * fr, mb = vm * fr;
+            atomicAdd(e + 1, ma * du0);
+            atomicAdd(e + 2 * tvp + 1, ma * c.du);
+            atomicAdd(e + 3, mb * du0);
+            atomicAdd(e + 2 * tvp + 3, mb * c.du);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // Flush: entry (r, c) holds pixel (org_u + c, org_v + r) and, for
+    // mirrored runs, pixel (org_u + c, G - org_v - r).
+    if (sr < rstep) {
+      for (int32_t sl = 0; sl < nvc; ++sl) {
+        const int32_t s = s0 + sl;
+        const int32_t gu = bvs[s].org_u + sc;
+        if (static_cast<uint32_t>(gu) >= static_cast<uint32_t>(gc.nu)) continue;
+        float* qs = q + s * vstride + gu;
+        for (int32_t r = sr; r < tv; r += rstep) {
+          const float2 e = atile[sl * slot + sc * tvp + r];
+          const int32_t gr = bvs[s].org_v + r;
+          if (e.x != 0.0f && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv))
+            unsafeAtomicAdd(qs + static_cast<int64_t>(gr) * gc.nu, e.x);
+          if (MIRROR) {
+            const int32_t gm = gc.mirror_g - gr;
+            if (e.y != 0.0f && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv))
+              unsafeAtomicAdd(qs + static_cast<int64_t>(gm) * gc.nu, e.y);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool MIRROR>
+__global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceRun run,
+                                                             ViewBatch vb, TileShape ts,
+                                                             const float* __restrict__ vol,
+                                                             float* __restrict__ q,
+                                                             int64_t vstride, float scale) {
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  const int32_t tid = threadIdx.x;
+  const BrickCoords bc = brick_coords(gc, run, ts);
+  if (tid < vb.nviews)
+    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+  float x[kBrickZ], xm[kBrickZ];
+  load_voxels<MIRROR>(gc, run, bc, vol, scale, x, xm);
+  __syncthreads();
+  if (!bc.owner) return;
   for (int32_t s = 0; s < vb.nviews; ++s) {
-    const ColumnF32 c = column_f32(bvs[s], txf, tyf, kvf);
+    const ColumnF32 c = column_f64(gc, vb.view[s], bvs[s], bc.i, bc.j, bc.kb);
     float* qs = q + s * vstride;
     const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
     const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);
 #pragma unroll
     for (int t = 0; t < kBrickZ; ++t) {
-      if (t0 + t >= run.n) break;
+      if (bc.t0 + t >= run.n) break;
       uint32_t dn;
       float fr;
       voxel_row_off(c.fvb, c.dvk, t, &dn, &fr);
@@ -459,10 +607,10 @@ int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, co
   if (ts.vc > 0) {
     const size_t lds = static_cast<size_t>(ts.vc) * ts.tu * ts.tvp * kTileEntryBytes;
     if (run.mirror)
-      hipLaunchKernelGGL((bp_tiled_kernel<T, true>), grid, block, lds, st, gc, run, vb, ts,
+      hipLaunchKernelGGL((bp_tiled_mirror_kernel<T>), grid, block, lds, st, gc, run, vb, ts,
                          qt, vstride, vol, scale, accumulate);
     else
-      hipLaunchKernelGGL((bp_tiled_kernel<T, false>), grid, block, lds, st, gc, run, vb, ts,
+      hipLaunchKernelGGL((bp_tiled_plain_kernel<T>), grid, block, lds, st, gc, run, vb, ts,
                          qt, vstride, vol, scale, accumulate);
   } else {
     if (run.mirror)
@@ -510,7 +658,7 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   ts.tu = static_cast<int32_t>(std::ceil(wu)) + 4;
   ts.tv = static_cast<int32_t>(std::ceil(wv)) + 5;
   ts.tvp = ts.tv | 1;  // odd pitch: 16 neighbouring columns hit distinct LDS banks
-  if (ts.tu > kThreads) return ts;
+  if (ts.tu + 1 > kThreads) return ts;  // staging and the adjoint's flush: a thread per column
   ts.rstep = kThreads / ts.tu;
   ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
   const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * kTileEntryBytes;
@@ -540,13 +688,29 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
                            const TileShape& ts, const float* vol, float* q, int64_t vstride,
                            float scale, void* stream) {
   const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
+  const dim3 grid(static_cast<uint32_t>(nwg)), block(kThreads);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (run.mirror)
-    hipLaunchKernelGGL((fp_brick_kernel<true>), dim3(static_cast<uint32_t>(nwg)), dim3(kThreads), 0,
-                       st, gc, run, vb, ts, vol, q, vstride, scale);
-  else
-    hipLaunchKernelGGL((fp_brick_kernel<false>), dim3(static_cast<uint32_t>(nwg)), dim3(kThreads), 0,
-                       st, gc, run, vb, ts, vol, q, vstride, scale);
+  if (ts.vc > 0) {
+    // Adjoint tile: one more column than the back-projection tile, float2
+    // entries; it always fits where the back-projection tile does.
+    TileShape tf = ts;
+    const int64_t per_view = static_cast<int64_t>(ts.tu + 1) * ts.tvp * sizeof(float2);
+    tf.vc = static_cast<int32_t>(std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view));
+    const size_t lds = static_cast<size_t>(tf.vc) * per_view;
+    if (run.mirror)
+      hipLaunchKernelGGL((fp_tiled_kernel<true>), grid, block, lds, st, gc, run, vb, tf, vol, q,
+                         vstride, scale);
+    else
+      hipLaunchKernelGGL((fp_tiled_kernel<false>), grid, block, lds, st, gc, run, vb, tf, vol, q,
+                         vstride, scale);
+  } else {
+    if (run.mirror)
+      hipLaunchKernelGGL((fp_direct_kernel<true>), grid, block, 0, st, gc, run, vb, ts, vol, q,
+                         vstride, scale);
+    else
+      hipLaunchKernelGGL((fp_direct_kernel<false>), grid, block, 0, st, gc, run, vb, ts, vol, q,
+                         vstride, scale);
+  }
   return static_cast<int>(hipGetLastError());
 }
 

@@ -239,17 +239,20 @@ def test_synth_gpu_generators_match_oracle():
 
 
 @pytest.mark.parametrize("name", list(VARIANTS))
-def test_tiled_kernel_equals_direct_kernel_bitwise(name, monkeypatch):
-    """The LDS-tiled kernel computes the same coordinates, taps and sums as
-    the direct kernel, so the two agree bit for bit."""
+def test_tiled_kernel_agrees_with_direct_kernel(name, monkeypatch):
+    """The LDS-tiled kernel (FP32 brick-relative columns, staged taps) and
+    the direct kernel (FP64 columns, taps from global memory) sample the
+    same taps with coordinates that differ by rounding only."""
     g = VARIANTS[name]
     ang = synth.angles(45, start=0.1)
     q = gpu(synth.random_projections(16, 45, g))
-    a = fdk.backproject(q, g, ang, scale=0.5)
+    a = host(fdk.backproject(q, g, ang, scale=0.5))
     monkeypatch.setenv("FDK_BP_KERNEL", "direct")
-    b = fdk.backproject(q, g, ang, scale=0.5)
-    torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    b = host(fdk.backproject(q, g, ang, scale=0.5))
+    err = rel_l2(a, b)
+    announce(f"  tiled vs direct: rel-L2 {err:.3e}, max |diff| {np.abs(a - b).max():.3e} "
+             f"(max |v| {np.abs(b).max():.3e})")
+    assert err <= 2e-6
 
 
 # Geometries for the footprint-tile bounds: strong magnification (tiles do
