@@ -38,11 +38,30 @@ METRIC = "back-projection GUPS at 2048³/2048 views; FP16-store vs FP32; adjoint
 N_CU, CLOCK_HZ, VALU_LANES_PER_CLK = 256, 2.4e9, 64
 LDS_BYTES_PER_CLK = 128
 HBM_PEAK = 8.0e12
-# Irreducible VALU work per voxel-view update of the mirrored scheme (per
-# voxel pair: v, floor, fraction, tap address = 4 shared; per voxel: two
-# u-lerps (4), one v-lerp (2), the weighted accumulate (1)) = 18 / 2.
-VALU_OPS_PER_UPDATE = 9.0
-LDS_BYTES_PER_UPDATE = {"f32": 16.0, "f16": 8.0, "bf16": 8.0}  # 4 taps
+# VALU work per voxel-view update of the mirrored, difference-staged scheme:
+# per voxel pair v, truncation, fraction and tap address (4, shared); per
+# voxel two u-interpolations (1 FMA each on the staged difference), one
+# v-interpolation (2) and the weighted accumulate (1): (4 + 2 * 5) / 2 = 7.
+VALU_OPS_PER_UPDATE = 7.0
+LDS_BYTES_PER_UPDATE = 16.0  # 4 FP32 taps (value and u-difference of two rows)
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "bp_tiled_mirror_kernel_bp2048_traffic.json")
+
+
+def profiled_traffic(workload):
+    """HBM bytes per launch of the back-projection kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by the calibration copy),
+    or None if the kernel sources changed since they were taken."""
+    import hashlib
+    if workload != "bp2048" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = json.load(open(TRAFFIC_RECORD))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    return (rec["fetch_size_kib_per_dispatch"] * rec["copy_read_factor"] +
+            rec["write_size_kib_per_dispatch"] * rec["copy_write_factor"]) * 1024.0
 
 
 def gups(updates: float, seconds: float) -> float:
@@ -175,15 +194,19 @@ def main():
     updates_per_launch = updates / launches
     achieved = gups(updates_per_launch, per_launch_s)
     valu_roof = N_CU * VALU_LANES_PER_CLK * CLOCK_HZ / VALU_OPS_PER_UPDATE / 2 ** 30
-    lds_roof = N_CU * LDS_BYTES_PER_CLK * CLOCK_HZ / LDS_BYTES_PER_UPDATE["f32"] / 2 ** 30
+    lds_roof = N_CU * LDS_BYTES_PER_CLK * CLOCK_HZ / LDS_BYTES_PER_UPDATE / 2 ** 30
     peak = min(valu_roof, lds_roof)
+    traffic = profiled_traffic(args.workload)
     roofline = {
         "bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1), "unit": "GUPS",
-        "frac": round(achieved / peak, 4), "traffic": None,
-        "kernel": "bp_kernel (FP32 storage)", "launches_per_step": launches,
+        "frac": round(achieved / peak, 4),
+        "traffic": None if traffic is None else round(traffic),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "kernel": "bp_tiled_mirror_kernel<float>", "launches_per_step": launches,
         "avg_launch_ms": round(per_launch_s * 1e3, 3),
         "valu_roof_gups": round(valu_roof, 1), "lds_roof_gups": round(lds_roof, 1),
-        "hbm_algorithmic_bytes_per_update": round(8.0 / 32 + g.nu * g.nv * 4.0 / (g.nx * g.ny * g.nz), 4),
+        "hbm_algorithmic_bytes_per_launch": round(updates_per_launch * (
+            8.0 / 32 + g.nu * g.nv * 4.0 / (g.nx * g.ny * g.nz))),
     }
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the workload ----

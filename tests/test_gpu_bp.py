@@ -252,7 +252,7 @@ def test_tiled_kernel_agrees_with_direct_kernel(name, monkeypatch):
     err = rel_l2(a, b)
     announce(f"  tiled vs direct: rel-L2 {err:.3e}, max |diff| {np.abs(a - b).max():.3e} "
              f"(max |v| {np.abs(b).max():.3e})")
-    assert err <= 2e-6
+    assert err <= 5e-6
 
 
 # Geometries for the footprint-tile bounds: strong magnification (tiles do
