@@ -80,11 +80,13 @@ __device__ __forceinline__ float buf_load<bf16_t>(__amdgpu_buffer_rsrc_t r, uint
 // brick origin column so every FP32 term is a small offset).
 struct BrickView {
   float uo, vo, au, bu, av, bv, zo, ci, cj;
-  int32_t org_u, org_v, pad;
+  int32_t org_u, org_v;
+  int32_t inside;  // the tile (columns org_u .. org_u + tu, its rows and mirror rows) is on the detector
 };
 
 __device__ BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i_lo, int32_t i_hi,
-                                 int32_t j_lo, int32_t j_hi, int32_t kb) {
+                                 int32_t j_lo, int32_t j_hi, int32_t kb, int32_t tu = 0,
+                                 int32_t tv = 0) {
   const double k0 = static_cast<double>(kb) - gc.cz;
   const double k1 = static_cast<double>(kb + kBrickZ - 1) - gc.cz;
   // u is a ratio of functions affine in (i, j) and v is affine in k at
@@ -115,7 +117,10 @@ __device__ BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i
   b.zo = static_cast<float>(zo);
   b.ci = static_cast<float>(g.ci);
   b.cj = static_cast<float>(g.cj);
-  b.pad = 0;
+  const bool cols_in = b.org_u >= 0 && b.org_u + tu < gc.nu;
+  const bool rows_in = b.org_v >= 0 && b.org_v + tv <= gc.nv;
+  const bool mirror_in = gc.mirror_g - b.org_v < gc.nv && gc.mirror_g - b.org_v - tv + 1 >= 0;
+  b.inside = tu > 0 && cols_in && rows_in && mirror_in;
   return b;
 }
 
@@ -194,7 +199,8 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   const int32_t kb = run.k_first + t0;
   const float kvf = static_cast<float>(gc.kv);
 
-  if (tid < vb.nviews) bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb);
+  if (tid < vb.nviews)
+    bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb, ts.tu, ts.tv);
   __syncthreads();
 
   float acc[kBrickZ], accm[kBrickZ];
@@ -214,33 +220,46 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     float4 pre[kPrefetchSlots];
 
     // Issue the loads of views [s0, s0 + nvc) into pre[]: raw (q(u), q(u+1))
-    // for the row and for its mirror row.
+    // for the row and for its mirror row. Views whose tile lies on the
+    // detector skip the range checks.
     auto load_stage = [&](int32_t s0, int32_t nvc) {
       int32_t sl = 0, rr = 0;
+      __amdgpu_buffer_rsrc_t rsrc;
+      int32_t org_v = 0, inside = 0;
+      uint32_t c0 = 0, c1 = 0;
 #pragma unroll
       for (int m = 0; m < kPrefetchSlots; ++m) {
         if (sl < nvc) {
+          if (rr == 0) {  // uniform: new view
+            const int32_t s = s0 + sl;
+            rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(q + s * vstride), 0, nrec,
+                                                     kBufferWord3);
+            const int32_t gu = bvs[s].org_u + sc;
+            org_v = bvs[s].org_v;
+            inside = bvs[s].inside;
+            c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
+                     ? static_cast<uint32_t>(gu) * es : kBadCol;
+            c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
+                     ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
+          }
           const int32_t r = sr + rr * rstep;
           if (stager && r < tv) {
-            const int32_t s = s0 + sl;
-            const __amdgpu_buffer_rsrc_t rsrc =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(q + s * vstride), 0, nrec,
-                                                  kBufferWord3);
-            const int32_t gu = bvs[s].org_u + sc;
-            const uint32_t c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
-                                    ? static_cast<uint32_t>(gu) * es : kBadCol;
-            const uint32_t c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
-                                    ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
-            const int32_t gr = bvs[s].org_v + r;
-            const uint32_t ro = static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
-                                    ? __umul24(static_cast<uint32_t>(gr), row_es) : kBadRow;
+            const int32_t gr = org_v + r;
+            const int32_t gm = gc.mirror_g - gr;
+            uint32_t ro, rm;
+            if (inside) {
+              ro = __umul24(static_cast<uint32_t>(gr), row_es);
+              rm = __umul24(static_cast<uint32_t>(gm), row_es);
+            } else {
+              ro = static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
+                       ? __umul24(static_cast<uint32_t>(gr), row_es) : kBadRow;
+              rm = static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
+                       ? __umul24(static_cast<uint32_t>(gm), row_es) : kBadRow;
+            }
             float4 p;
             p.x = buf_load<T>(rsrc, ro + c0);
             p.y = buf_load<T>(rsrc, ro + c1);
             if (MIRROR) {
-              const int32_t gm = gc.mirror_g - gr;
-              const uint32_t rm = static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
-                                      ? __umul24(static_cast<uint32_t>(gm), row_es) : kBadRow;
               p.z = buf_load<T>(rsrc, rm + c0);
               p.w = buf_load<T>(rsrc, rm + c1);
             } else {
@@ -459,18 +478,31 @@ __device__ __forceinline__ BrickCoords brick_coords(const GeoConst& gc, const Sl
   return bc;
 }
 
+// Slot order of a lane in the adjoint. Lanes of a wave that share a detector
+// column (along the rays) would otherwise add to the same LDS or global
+// address in the same instruction, which serialises; rotating each lane's
+// walk over its 16 slots by (tx + 4 ty) mod 16 puts such lanes on
+// different rows.
+__device__ __forceinline__ uint32_t slot_rotation() {
+  const uint32_t tx = threadIdx.x % kBrickX, ty = (threadIdx.x / kBrickX) & 3u;
+  return (tx + 4u * ty) & (kBrickZ - 1);
+}
+
+// Voxel values of the thread's column, scaled, in the lane's slot order:
+// x[t] is slot (t + rot) mod 16.
 template <bool MIRROR>
 __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& run,
                                             const BrickCoords& bc, const float* __restrict__ vol,
-                                            float scale, float* x, float* xm) {
+                                            float scale, uint32_t rot, float* x, float* xm) {
   const int64_t slice = static_cast<int64_t>(gc.nx) * gc.ny;
   const int64_t col = static_cast<int64_t>(bc.j) * gc.nx + bc.i;
 #pragma unroll
   for (int t = 0; t < kBrickZ; ++t) {
-    const bool in = bc.owner && (bc.t0 + t < run.n);
-    x[t] = in ? scale * vol[static_cast<int64_t>(run.loc_lo + bc.t0 + t) * slice + col] : 0.0f;
+    const int32_t sl = static_cast<int32_t>((t + rot) & (kBrickZ - 1));
+    const bool in = bc.owner && (bc.t0 + sl < run.n);
+    x[t] = in ? scale * vol[static_cast<int64_t>(run.loc_lo + bc.t0 + sl) * slice + col] : 0.0f;
     xm[t] = (MIRROR && in)
-                ? scale * vol[static_cast<int64_t>(run.loc_hi - bc.t0 - t) * slice + col]
+                ? scale * vol[static_cast<int64_t>(run.loc_hi - bc.t0 - sl) * slice + col]
                 : 0.0f;
   }
 }
@@ -487,8 +519,9 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   const BrickCoords bc = brick_coords(gc, run, ts);
   if (tid < vb.nviews)
     bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+  const uint32_t rot = slot_rotation();
   float x[kBrickZ], xm[kBrickZ];
-  load_voxels<MIRROR>(gc, run, bc, vol, scale, x, xm);
+  load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
   __syncthreads();
 
   const float kvf = static_cast<float>(gc.kv);
@@ -510,7 +543,7 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
         for (int t = 0; t < kBrickZ; ++t) {
           uint32_t dn;
           float fr;
-          voxel_row_off(c.fvb, c.dvk, t, &dn, &fr);
+          voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
           float* e = base + 2 * dn;  // float2 entries: (main, mirror)
           const float val = c.w * x[t];
           const float wa = val - val * fr, wb = val * fr;
@@ -566,8 +599,9 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
   const BrickCoords bc = brick_coords(gc, run, ts);
   if (tid < vb.nviews)
     bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+  const uint32_t rot = slot_rotation();
   float x[kBrickZ], xm[kBrickZ];
-  load_voxels<MIRROR>(gc, run, bc, vol, scale, x, xm);
+  load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
   __syncthreads();
   if (!bc.owner) return;
   for (int32_t s = 0; s < vb.nviews; ++s) {
@@ -577,10 +611,11 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
     const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);
 #pragma unroll
     for (int t = 0; t < kBrickZ; ++t) {
-      if (bc.t0 + t >= run.n) break;
+      const int32_t sl = static_cast<int32_t>((t + rot) & (kBrickZ - 1));
+      if (bc.t0 + sl >= run.n) continue;
       uint32_t dn;
       float fr;
-      voxel_row_off(c.fvb, c.dvk, t, &dn, &fr);
+      voxel_row_off(c.fvb, c.dvk, sl, &dn, &fr);
       const int32_t n = nb + static_cast<int32_t>(dn);
       splat(qs, gc.nu, gc.nv, a, c.du, n, n + 1, fr, c.w * x[t]);
       if (MIRROR) {
