@@ -291,3 +291,19 @@ def test_bp_edge_geometries(name):
     fp = host(fdk.forward_project(gpu(x), g, ang))
     fref = oracle.forward_project(g, ang, x.astype(np.float64))
     assert rel_l2(fp, fref) <= 1e-5
+
+
+@pytest.mark.parametrize("nu", [1000, 2048, 4096])
+@pytest.mark.parametrize("kind", ["ramlak", "shepp-logan"])
+def test_filter_fft_path_matches_oracle(nu, kind):
+    """Rows above 256 pixels take the FFT path (2048: 4096-point FFTs,
+    4096: 8192-point FFTs in 96 KB of LDS); an odd row count exercises the
+    unpaired last row."""
+    g = BASE.replace(nu=nu, nv=3, off_u=0.25, sod=4.0 * nu, sdd=8.0 * nu)
+    ang = synth.angles(3)
+    e = np.random.default_rng(nu).uniform(0, 50, (3, g.nv, g.nu)).astype(np.float32)
+    ref = oracle.filter(g, e.astype(np.float64), kind)
+    got = host(fdk.filter(gpu(e), g, ang, kind=kind))
+    err = rel_l2(got, ref)
+    announce(f"  filter nu={nu} {kind}: rel-L2 {err:.3e}")
+    assert err <= 1e-5
