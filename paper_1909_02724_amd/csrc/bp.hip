@@ -57,19 +57,35 @@ __device__ __forceinline__ float tap(const T* __restrict__ qs, int32_t nu, int32
              : 0.0f;
 }
 
+// Raw buffer loads for the staging prefetch: the bits stay untouched in
+// registers (no wait on the load) and are converted when the tile is written.
 template <typename T>
-__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+__device__ __forceinline__ uint32_t buf_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t off);
 template <>
-__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+__device__ __forceinline__ uint32_t buf_load_raw<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
 }
 template <>
-__device__ __forceinline__ float buf_load<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return to_f32(f16_t{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)});
+__device__ __forceinline__ uint32_t buf_load_raw<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
 }
 template <>
-__device__ __forceinline__ float buf_load<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return to_f32(bf16_t{__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)});
+__device__ __forceinline__ uint32_t buf_load_raw<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ float raw_to_f32(uint32_t bits);
+template <>
+__device__ __forceinline__ float raw_to_f32<float>(uint32_t bits) {
+  return __uint_as_float(bits);
+}
+template <>
+__device__ __forceinline__ float raw_to_f32<f16_t>(uint32_t bits) {
+  return to_f32(f16_t{static_cast<uint16_t>(bits)});
+}
+template <>
+__device__ __forceinline__ float raw_to_f32<bf16_t>(uint32_t bits) {
+  return __uint_as_float(bits << 16);
 }
 
 // Per (brick, view) constants. With tx = i - i_lo, ty = j - j_lo and
@@ -217,7 +233,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     const uint32_t es = sizeof(T);
     const uint32_t row_es = static_cast<uint32_t>(gc.nu) * es;
     const uint32_t nrec = static_cast<uint32_t>(gc.nu) * static_cast<uint32_t>(gc.nv) * es;
-    float4 pre[kPrefetchSlots];
+    uint4 pre[kPrefetchSlots];  // raw bits of (q(u), q(u+1)) for the row and its mirror
 
     // Issue the loads of views [s0, s0 + nvc) into pre[]: raw (q(u), q(u+1))
     // for the row and for its mirror row. Views whose tile lies on the
@@ -256,14 +272,14 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
               rm = static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
                        ? __umul24(static_cast<uint32_t>(gm), row_es) : kBadRow;
             }
-            float4 p;
-            p.x = buf_load<T>(rsrc, ro + c0);
-            p.y = buf_load<T>(rsrc, ro + c1);
+            uint4 p;
+            p.x = buf_load_raw<T>(rsrc, ro + c0);
+            p.y = buf_load_raw<T>(rsrc, ro + c1);
             if (MIRROR) {
-              p.z = buf_load<T>(rsrc, rm + c0);
-              p.w = buf_load<T>(rsrc, rm + c1);
+              p.z = buf_load_raw<T>(rsrc, rm + c0);
+              p.w = buf_load_raw<T>(rsrc, rm + c1);
             } else {
-              p.z = p.w = 0.0f;
+              p.z = p.w = 0u;
             }
             pre[m] = p;
           }
@@ -283,8 +299,9 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
         if (sl < nvc) {
           const int32_t r = sr + rr * rstep;
           if (stager && r < tv) {
-            const float4 p = pre[m];
-            tile[sl * slot_entries + sc * tvp + r] = make_float4(p.x, p.y - p.x, p.z, p.w - p.z);
+            const float a0 = raw_to_f32<T>(pre[m].x), a1 = raw_to_f32<T>(pre[m].y);
+            const float b0 = raw_to_f32<T>(pre[m].z), b1 = raw_to_f32<T>(pre[m].w);
+            tile[sl * slot_entries + sc * tvp + r] = make_float4(a0, a1 - a0, b0, b1 - b0);
           }
         }
         if (++rr == rows) {
