@@ -96,6 +96,20 @@ fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews,
                       const float* e, void* q, fdk_dtype out_dtype,
                       fdk_filter_kind kind, void* stream);
 
+/* The filtering stage of fdk_filter on a band of detector rows: rows
+ * [v0, v0 + nrows) of views [view0, view0 + nviews). Element (s, r, u) of
+ * the band is e[s * e_view_stride + r * Nu + u] on input and
+ * q[s * q_view_stride + r * Nu + u] on output (strides in elements), so the
+ * output may be the band's rows inside a full (nviews, Nv, Nu) array. Each
+ * row's result equals fdk_filter's for the same detector row. Used to filter
+ * only the rows a volume slab projects to.
+ * Errors: as fdk_filter, plus FDK_ERR_INVALID_ARG for a band outside
+ * [0, Nv) or a view stride smaller than nrows * Nu. */
+fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
+                           int32_t nrows, const float* e, int64_t e_view_stride, void* q,
+                           int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
+                           void* stream);
+
 /* Back-projection, Alg. 2 computed as Alg. 4. For every voxel (i, j, k)
  * the slab holds, with [x, y, z] = P_s [i, j, k, 1], f = 1/z, W = f^2,
  * (u, v) = (x f, y f):

@@ -97,6 +97,10 @@ def lib():
         L.fdk_filter.restype = C.c_int
         L.fdk_filter.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int,
                                  C.c_int, C.c_void_p]
+        L.fdk_filter_rows.restype = C.c_int
+        L.fdk_filter_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int,
+                                      C.c_void_p]
         L.fdk_fdk_scale.restype = C.c_double
         L.fdk_fdk_scale.argtypes = [P]
         L.fdk_last_error.restype = C.c_char_p
@@ -185,21 +189,32 @@ def forward_project(vol: torch.Tensor, geom, angles, *, view0: int = 0,
 
 
 def filter(e: torch.Tensor, geom, angles, *, view0: int = 0, kind: str = "ramlak",
-           dtype: torch.dtype = torch.float32, out: torch.Tensor | None = None) -> torch.Tensor:
+           dtype: torch.dtype = torch.float32, out: torch.Tensor | None = None,
+           rows: tuple[int, int] | None = None) -> torch.Tensor:
     """Filtering stage (Alg. 1): cosine weight and ramp convolution of
-    float32 line integrals (nviews, Nv, Nu); output in `dtype` storage."""
-    _dev(e, "e")
-    if e.dtype != torch.float32 or e.dim() != 3 or e.shape[1:] != (geom.nv, geom.nu):
-        raise ValueError(f"e must be float32 (nviews, {geom.nv}, {geom.nu})")
+    float32 line integrals (nviews, Nv, Nu); output in `dtype` storage.
+
+    rows=(v0, nrows) filters only detector rows [v0, v0 + nrows): `e` and
+    `out` are then (nviews, nrows, Nu) and may be views into larger arrays
+    (row-contiguous, any view stride)."""
+    if not e.is_cuda:
+        raise ValueError("e must be a GPU tensor (no CPU fallback)")
+    v0, nrows = (0, geom.nv) if rows is None else (int(rows[0]), int(rows[1]))
+    if e.dtype != torch.float32 or e.dim() != 3 or tuple(e.shape[1:]) != (nrows, geom.nu):
+        raise ValueError(f"e must be float32 (nviews, {nrows}, {geom.nu})")
     if out is None:
         out = torch.empty(e.shape, dtype=dtype, device=e.device)
-    _dev(out, "out")
-    if out.dtype not in _DTYPES or out.shape != e.shape:
+    if not out.is_cuda or out.dtype not in _DTYPES or out.shape != e.shape:
         raise ValueError("out must match e's shape with a float32/float16/bfloat16 dtype")
+    for t, name in ((e, "e"), (out, "out")):
+        if t.stride(2) != 1 or (nrows > 1 and t.stride(1) != geom.nu):
+            raise ValueError(f"{name} rows must be contiguous")
     cg, _keep = _cgeom(geom, angles)
-    _check(lib().fdk_filter(C.byref(cg), view0, e.shape[0], C.c_void_p(e.data_ptr()),
-                            C.c_void_p(out.data_ptr()), _DTYPES[out.dtype], _FILTERS[kind],
-                            _stream(e)))
+    _check(lib().fdk_filter_rows(C.byref(cg), view0, e.shape[0], v0, nrows,
+                                 C.c_void_p(e.data_ptr()), e.stride(0) if e.shape[0] > 1 else nrows * geom.nu,
+                                 C.c_void_p(out.data_ptr()),
+                                 out.stride(0) if out.shape[0] > 1 else nrows * geom.nu,
+                                 _DTYPES[out.dtype], _FILTERS[kind], _stream(e)))
     return out
 
 

@@ -266,8 +266,10 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
   return ok();
 }
 
-fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews, const float* e,
-                      void* q, fdk_dtype out_dtype, fdk_filter_kind kind, void* stream) {
+fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
+                           int32_t nrows, const float* e, int64_t e_view_stride, void* q,
+                           int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
+                           void* stream) {
   fdk_status st = check_geometry(g);
   if (st) return st;
   if ((st = check_views(g, view0, nviews))) return st;
@@ -276,19 +278,34 @@ fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews, cons
   if (kind != FDK_RAMLAK && kind != FDK_SHEPP_LOGAN)
     return fail(FDK_ERR_UNSUPPORTED, "unknown filter kind %d", (int)kind);
   if (g->nu > 8192) return fail(FDK_ERR_UNSUPPORTED, "filter rows above 8192 pixels (Nu = %d)", g->nu);
-  if (nviews == 0) return ok();
+  if (v0 < 0 || nrows < 0 || (int64_t)v0 + nrows > g->nv)
+    return fail(FDK_ERR_INVALID_ARG, "row band [%d, %d + %d) is outside [0, %d)", v0, v0, nrows,
+                g->nv);
+  if (nviews == 0 || nrows == 0) return ok();
+  const int64_t band = (int64_t)nrows * g->nu;
+  if (e_view_stride < band || q_view_stride < band)
+    return fail(FDK_ERR_INVALID_ARG, "view stride smaller than the band (%lld elements)",
+                (long long)band);
   if (!e || !q) return fail(FDK_ERR_INVALID_ARG, "projection pointer is NULL");
-  const size_t nbytes_in = (size_t)nviews * g->nv * g->nu * 4;
-  const size_t nbytes_out = (size_t)nviews * g->nv * g->nu * dtype_size(out_dtype);
+  const size_t nbytes_in = (size_t)((nviews - 1) * e_view_stride + band) * 4;
+  const size_t nbytes_out = (size_t)((nviews - 1) * q_view_stride + band) * dtype_size(out_dtype);
   const char* a = reinterpret_cast<const char*>(e);
   const char* b = static_cast<const char*>(q);
   if (a < b + nbytes_out && b < a + nbytes_in)
     return fail(FDK_ERR_INVALID_ARG, "filter input and output overlap");
   const fdk::GeoConst gc = make_geo(g);
-  if (int err = fdk::launch_filter(gc, g->du, g->dv, g->sod, g->sdd, nviews * g->nv, e, q,
-                                   out_dtype, kind, stream))
+  const fdk::RowBand rb{nviews, v0, nrows, e_view_stride, q_view_stride};
+  if (int err = fdk::launch_filter(gc, g->du, g->dv, g->sod, g->sdd, rb, e, q, out_dtype, kind,
+                                   stream))
     return fail(FDK_ERR_HIP, "filter launch failed: HIP error %d", err);
   return ok();
+}
+
+fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews, const float* e,
+                      void* q, fdk_dtype out_dtype, fdk_filter_kind kind, void* stream) {
+  if (!g) return fail(FDK_ERR_INVALID_ARG, "geometry pointer is NULL");
+  const int64_t full = (int64_t)g->nu * g->nv;
+  return fdk_filter_rows(g, view0, nviews, 0, g->nv, e, full, q, full, out_dtype, kind, stream);
 }
 
 }  // extern "C"

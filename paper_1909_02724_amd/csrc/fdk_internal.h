@@ -81,8 +81,14 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
                            const TileShape& ts, const float* vol, float* q, int64_t view_stride,
                            float scale, void* stream);
 int launch_fill_zero(float* p, int64_t n, void* stream);
+// Filter rows [v0, v0 + band) of nviews views; row m of the launch is view
+// m / band, detector row v0 + m % band; view strides in elements.
+struct RowBand {
+  int32_t nviews, v0, band;
+  int64_t e_stride, q_stride;
+};
 int launch_filter(const GeoConst& gc, double du, double dv, double sod, double sdd,
-                  int32_t nrows, const float* e, void* q, fdk_dtype out_dtype,
+                  const RowBand& rb, const float* e, void* q, fdk_dtype out_dtype,
                   fdk_filter_kind kind, void* stream);
 
 }  // namespace fdk

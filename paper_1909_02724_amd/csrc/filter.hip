@@ -60,23 +60,34 @@ __device__ __forceinline__ float cos_weight(const GeoConst& gc, double du, doubl
   return static_cast<float>(sdd / sqrt(sdd * sdd + aa * aa + bb * bb));
 }
 
+// Row m of a band launch: input and output row pointers and detector row.
+struct BandRow {
+  int64_t ein, qout;  // element offsets of the row in e and q
+  int32_t b;          // detector row
+};
+__device__ __forceinline__ BandRow band_row(const RowBand& rb, int32_t nu, int64_t m) {
+  const int64_t s = m / rb.band, r = m - s * rb.band;
+  return BandRow{s * rb.e_stride + r * nu, s * rb.q_stride + r * nu,
+                 static_cast<int32_t>(rb.v0 + r)};
+}
+
 template <typename OutT>
 __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
-    GeoConst gc, double du, double dv, double sdd, double tau, int kind,
+    GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
     const float* __restrict__ e, OutT* __restrict__ q) {
   extern __shared__ float lds[];
   const int32_t nu = gc.nu;
   float* et = lds;      // cosine-weighted row
   float* h = lds + nu;  // tau * h(|n|), n in [0, nu)
-  const int64_t row = blockIdx.x;
-  const int32_t b = static_cast<int32_t>(row % gc.nv);
-  const float* er = e + row * nu;
+  const BandRow br = band_row(rband, nu, blockIdx.x);
+  const int32_t b = br.b;
+  const float* er = e + br.ein;
   for (int32_t a = threadIdx.x; a < nu; a += kFilterThreads) {
     et[a] = er[a] * cos_weight(gc, du, dv, sdd, a, b);
     h[a] = static_cast<float>(tau * ramp_tap(kind, a, tau));
   }
   __syncthreads();
-  OutT* qr = q + row * nu;
+  OutT* qr = q + br.qout;
   for (int32_t a = threadIdx.x; a < nu; a += kFilterThreads) {
     float acc = 0.0f;
     for (int32_t n = 0; n < nu; ++n) {
@@ -114,8 +125,8 @@ __device__ __forceinline__ int32_t bitrev(int32_t n, int32_t logl) {
 
 template <typename OutT>
 __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(
-    GeoConst gc, double du, double dv, double sdd, double tau, int kind, int32_t logl,
-    int32_t nrows, const float* __restrict__ e, OutT* __restrict__ q) {
+    GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
+    int32_t logl, int64_t nrows, const float* __restrict__ e, OutT* __restrict__ q) {
   extern __shared__ float2 flds[];
   const int32_t L = 1 << logl, nu = gc.nu;
   float2* x = flds;       // L complex points
@@ -141,17 +152,18 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(
   }
   __syncthreads();
 
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 2 * kFftRowPairs;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 2 * kFftRowPairs;  // launch rows
   for (int32_t p = 0; p < kFftRowPairs; ++p) {
     const int64_t ra = row0 + 2 * p, rb = ra + 1;
     if (ra >= nrows) break;  // uniform
     const bool has_b = rb < nrows;
-    const int32_t va = static_cast<int32_t>(ra % gc.nv), vb = static_cast<int32_t>(rb % gc.nv);
+    const BandRow rowa = band_row(rband, nu, ra);
+    const BandRow rowb = band_row(rband, nu, has_b ? rb : ra);
     for (int32_t n = threadIdx.x; n < L; n += kFilterThreads) {
       float re = 0.0f, im = 0.0f;
       if (n < nu) {
-        re = e[ra * nu + n] * cos_weight(gc, du, dv, sdd, n, va);
-        if (has_b) im = e[rb * nu + n] * cos_weight(gc, du, dv, sdd, n, vb);
+        re = e[rowa.ein + n] * cos_weight(gc, du, dv, sdd, n, rowa.b);
+        if (has_b) im = e[rowb.ein + n] * cos_weight(gc, du, dv, sdd, n, rowb.b);
       }
       x[bitrev(n, logl)] = make_float2(re, im);
     }
@@ -178,17 +190,18 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(
     fft_inplace(x, tw, logl);
     for (int32_t n = threadIdx.x; n < nu; n += kFilterThreads) {
       const float2 v = x[n];
-      store_q(q + ra * nu + n, v.x);
-      if (has_b) store_q(q + rb * nu + n, -v.y);
+      store_q(q + rowa.qout + n, v.x);
+      if (has_b) store_q(q + rowb.qout + n, -v.y);
     }
     __syncthreads();
   }
 }
 
 template <typename OutT>
-int launch_filter_t(const GeoConst& gc, double du, double dv, double sdd, double tau, int kind,
-                    int32_t nrows, const float* e, void* q, hipStream_t st) {
+int launch_filter_t(const GeoConst& gc, const RowBand& rb, double du, double dv, double sdd,
+                    double tau, int kind, const float* e, void* q, hipStream_t st) {
   OutT* qt = static_cast<OutT*>(q);
+  const int64_t nrows = static_cast<int64_t>(rb.nviews) * rb.band;
   int32_t logl = 0;
   while ((1 << logl) < 2 * gc.nu - 1) ++logl;
   if (gc.nu > kDirectMaxNu && logl <= kFftMaxLog) {
@@ -202,29 +215,29 @@ int launch_filter_t(const GeoConst& gc, double du, double dv, double sdd, double
       if (err != hipSuccess) return static_cast<int>(err);
     }
     hipLaunchKernelGGL(filter_fft_kernel<OutT>, dim3(groups), dim3(kFilterThreads), lds, st, gc,
-                       du, dv, sdd, tau, kind, logl, nrows, e, qt);
+                       rb, du, dv, sdd, tau, kind, logl, nrows, e, qt);
   } else {
     const size_t lds = 2 * static_cast<size_t>(gc.nu) * sizeof(float);
-    hipLaunchKernelGGL(filter_direct_kernel<OutT>, dim3(nrows), dim3(kFilterThreads), lds, st, gc,
-                       du, dv, sdd, tau, kind, e, qt);
+    hipLaunchKernelGGL(filter_direct_kernel<OutT>, dim3(static_cast<uint32_t>(nrows)),
+                       dim3(kFilterThreads), lds, st, gc, rb, du, dv, sdd, tau, kind, e, qt);
   }
   return static_cast<int>(hipGetLastError());
 }
 
 }  // namespace
 
-int launch_filter(const GeoConst& gc, double du, double dv, double sod, double sdd, int32_t nrows,
-                  const float* e, void* q, fdk_dtype out_dtype, fdk_filter_kind kind,
-                  void* stream) {
+int launch_filter(const GeoConst& gc, double du, double dv, double sod, double sdd,
+                  const RowBand& rb, const float* e, void* q, fdk_dtype out_dtype,
+                  fdk_filter_kind kind, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double tau = du * sod / sdd;  // pixel pitch scaled to the rotation axis
   switch (out_dtype) {
     case FDK_F32:
-      return launch_filter_t<float>(gc, du, dv, sdd, tau, kind, nrows, e, q, st);
+      return launch_filter_t<float>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
     case FDK_F16:
-      return launch_filter_t<f16_t>(gc, du, dv, sdd, tau, kind, nrows, e, q, st);
+      return launch_filter_t<f16_t>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
     case FDK_BF16:
-      return launch_filter_t<bf16_t>(gc, du, dv, sdd, tau, kind, nrows, e, q, st);
+      return launch_filter_t<bf16_t>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
   }
   return static_cast<int>(hipErrorInvalidValue);
 }

@@ -108,6 +108,23 @@ def test_forward_and_filter_validation():
     assert "NULL" in L.fdk_last_error().decode()
 
 
+def test_filter_rows_validation():
+    L = fdk.lib()
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    band = 5 * GOOD.nu
+    assert L.fdk_filter_rows(C.byref(cg), 0, 2, 18, 5, FAKE, band, C.c_void_p(0x100000), band,
+                             0, 0, None) == 1
+    assert "row band" in L.fdk_last_error().decode()
+    assert L.fdk_filter_rows(C.byref(cg), 0, 2, 0, 5, FAKE, band - 1, C.c_void_p(0x100000), band,
+                             0, 0, None) == 1
+    assert "view stride" in L.fdk_last_error().decode()
+    assert L.fdk_filter_rows(C.byref(cg), 0, 2, 0, 5, C.c_void_p(0x1000), band,
+                             C.c_void_p(0x1000 + 8), band, 0, 0, None) == 1
+    assert "overlap" in L.fdk_last_error().decode()
+    # an empty band is a successful no-op (nothing enqueued)
+    assert L.fdk_filter_rows(C.byref(cg), 0, 2, 3, 0, FAKE, band, FAKE, band, 0, 0, None) == 0
+
+
 def test_fdk_scale():
     cg, keep = fdk._cgeom(GOOD, ANG)
     assert fdk.lib().fdk_fdk_scale(C.byref(cg)) == pytest.approx(math.pi * 100.0 ** 2 / 12)

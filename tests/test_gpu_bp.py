@@ -307,3 +307,22 @@ def test_filter_fft_path_matches_oracle(nu, kind):
     err = rel_l2(got, ref)
     announce(f"  filter nu={nu} {kind}: rel-L2 {err:.3e}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("nu", [200, 1000])
+def test_filter_rows_band_into_full_array(nu):
+    """fdk_filter_rows on a band of rows, written into the band's rows of a
+    full projection array, equals fdk_filter on those rows (and the oracle)."""
+    g = BASE.replace(nu=nu, nv=40, off_v=0.5)
+    ang = synth.angles(3)
+    e = np.random.default_rng(7).uniform(0, 20, (3, g.nv, g.nu)).astype(np.float32)
+    full = host(fdk.filter(gpu(e), g, ang, kind="shepp-logan"))
+    out = torch.zeros((3, g.nv, g.nu), dtype=torch.float32, device=DEV)
+    v0, nr = 11, 9
+    fdk.filter(gpu(e[:, v0:v0 + nr]), g, ang, kind="shepp-logan", rows=(v0, nr),
+               out=out[:, v0:v0 + nr])
+    got = host(out)
+    assert rel_l2(got[:, v0:v0 + nr], full[:, v0:v0 + nr]) <= 1e-6
+    assert np.abs(got[:, :v0]).max() == 0 and np.abs(got[:, v0 + nr:]).max() == 0
+    ref = oracle.filter(g, e.astype(np.float64), "shepp-logan")
+    assert rel_l2(got[:, v0:v0 + nr], ref[:, v0:v0 + nr]) <= 1e-5
