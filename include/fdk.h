@@ -136,8 +136,10 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
  * Every voxel of the slab adds scale * W * w_tap * vol(i,j,k) to each of its
  * four bilinear taps that lies inside the detector, with the identical
  * coordinates and weights the back-projector uses. vol: device FP32 slab.
- * q: device FP32 (nviews, Nv, Nu), overwritten unless FDK_ACCUMULATE. Uses
- * floating-point atomics, so the last bits vary from run to run.
+ * q: device FP32 (nviews, Nv, Nu), overwritten unless FDK_ACCUMULATE.
+ * Within a workgroup the splats are summed in 32-bit fixed point, scaled per
+ * brick and view so that no partial sum can overflow; the workgroups' sums
+ * meet in FP32 atomics, so the last bits vary from run to run.
  * Errors: as fdk_backproject. */
 fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nviews,
                                const float* vol, int32_t z0, int32_t nz_local,
