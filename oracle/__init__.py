@@ -15,6 +15,7 @@ Each wrapped routine names the passage of Chen et al. (SC'19) it follows:
   backproject_alg4    Alg. 4 (Theorems 1-3), written independently of Alg. 2
   forward_project     the exact transpose of backproject
   filter              Alg. 1: cosine weight, then ramp convolution per row
+  filter_rows         Alg. 1 on a list of detector rows
   phantom_project     analytic line integrals of an ellipsoid phantom
 """
 from __future__ import annotations
@@ -83,6 +84,8 @@ def lib():
         L.or_cos_weight.argtypes = [_DP, C.c_double, C.c_double]
         L.or_filter.restype = C.c_int
         L.or_filter.argtypes = [_DP, C.c_int64, C.c_int, _DP, _DP]
+        L.or_filter_rows.restype = C.c_int
+        L.or_filter_rows.argtypes = [_DP, C.c_int64, _IP, C.c_int, _DP, _DP]
         L.or_hash_fill.argtypes = [C.c_uint64, C.c_int64, _UP, C.c_int, _DP]
         _lib = L
     return _lib
@@ -247,6 +250,19 @@ def filter(geom, e, kind="ramlak") -> np.ndarray:
     assert e.shape[1:] == (geom.nv, geom.nu)
     out = np.zeros_like(e)
     if lib().or_filter(_d(gvec(geom)), e.shape[0], FILTERS[kind], _d(e), _d(out)):
+        raise MemoryError("oracle filter")
+    return out
+
+
+def filter_rows(geom, e_rows, rows_v, kind="ramlak") -> np.ndarray:
+    """Alg. 1 on a list of detector rows: e_rows (n, Nu); row m is detector
+    row rows_v[m], whose cosine weights depend on it."""
+    e = _f64(e_rows)
+    rv = np.ascontiguousarray(rows_v, dtype=np.int64)
+    assert e.ndim == 2 and e.shape == (rv.size, geom.nu)
+    out = np.zeros_like(e)
+    if lib().or_filter_rows(_d(gvec(geom)), rv.size, rv.ctypes.data_as(_IP), FILTERS[kind],
+                            _d(e), _d(out)):
         raise MemoryError("oracle filter")
     return out
 

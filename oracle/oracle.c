@@ -446,12 +446,27 @@ double or_cos_weight(const double* g, double u, double v) {
   return D / sqrt(D * D + a * a + b * b);
 }
 
-/* Alg. 1 for each row: E~ = E * F_cos point-wise, then
+/* Alg. 1 for one detector row b: E~ = E * F_cos point-wise, then
  * Q(u) = tau * sum_n h(u - n) E~(n), a direct linear convolution (zero
- * outside the row). e and out are (nviews, nv, nu). Returns -1 on
- * allocation failure. */
-int or_filter(const double* g, int64_t nviews, int kind, const double* e, double* out) {
-  const int64_t nu = G_NU(g), nv = G_NV(g);
+ * outside the row). h holds h(n) for n in [-nu, nu] at h[n + nu]; et is
+ * nu doubles of scratch. */
+static void filter_row(const double* g, const double* h, double tau, int64_t b,
+                       const double* row, double* et, double* qrow) {
+  const int64_t nu = G_NU(g);
+  for (int64_t n = 0; n < nu; ++n) et[n] = row[n] * or_cos_weight(g, (double)n, (double)b);
+  for (int64_t a = 0; a < nu; ++a) {
+    double acc = 0.0;
+    for (int64_t n = 0; n < nu; ++n) acc += h[a - n + nu] * et[n];
+    qrow[a] = tau * acc;
+  }
+}
+
+/* Alg. 1 on nrows rows of nu values; row m is detector row rows_v[m]
+ * (its cosine weights depend on it). e and out are (nrows, nu). Returns -1
+ * on allocation failure. */
+int or_filter_rows(const double* g, int64_t nrows, const int64_t* rows_v, int kind,
+                   const double* e, double* out) {
+  const int64_t nu = G_NU(g);
   const double tau = g[8] * g[12] / g[13];
   double* h = (double*)malloc((size_t)(2 * nu + 1) * sizeof(double));
   if (!h) return -1;
@@ -464,23 +479,26 @@ int or_filter(const double* g, int64_t nviews, int kind, const double* e, double
 #pragma omp atomic write
       failed = 1;
     }
-#pragma omp for collapse(2) schedule(static)
-    for (int64_t s = 0; s < nviews; ++s)
-      for (int64_t b = 0; b < nv; ++b) {
-        if (!et) continue;
-        const double* row = e + (s * nv + b) * nu;
-        double* qrow = out + (s * nv + b) * nu;
-        for (int64_t n = 0; n < nu; ++n) et[n] = row[n] * or_cos_weight(g, (double)n, (double)b);
-        for (int64_t a = 0; a < nu; ++a) {
-          double acc = 0.0;
-          for (int64_t n = 0; n < nu; ++n) acc += h[a - n + nu] * et[n];
-          qrow[a] = tau * acc;
-        }
-      }
+#pragma omp for schedule(static)
+    for (int64_t m = 0; m < nrows; ++m) {
+      if (!et) continue;
+      filter_row(g, h, tau, rows_v[m], e + m * nu, et, out + m * nu);
+    }
     free(et);
   }
   free(h);
   return failed ? -1 : 0;
+}
+
+/* Alg. 1 on whole views: e and out are (nviews, nv, nu). */
+int or_filter(const double* g, int64_t nviews, int kind, const double* e, double* out) {
+  const int64_t nv = G_NV(g);
+  int64_t* rows_v = (int64_t*)malloc((size_t)(nviews * nv) * sizeof(int64_t));
+  if (!rows_v) return -1;
+  for (int64_t m = 0; m < nviews * nv; ++m) rows_v[m] = m % nv;
+  const int rc = or_filter_rows(g, nviews * nv, rows_v, kind, e, out);
+  free(rows_v);
+  return rc;
 }
 
 /* Generated tap values for a list of counters (for tests of the
