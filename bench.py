@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Back-projection benchmark: GUPS of the FDK back-projector on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload bp2048]
+    python bench.py [--steps K] [--warmup W] [--workload bp2048|slab4096]
 
 Workload (default): 2048^3 FP32 volume, 2048 views of 2048^2 pixels over a
 full circle, views in launches of 32. A step is one complete back-projection
@@ -18,6 +18,16 @@ timed on a bounded sample of the same workload on this host.
 Inputs are synthetic and seeded: the analytic line integrals of a sum of 32
 random ellipsoids (stand-in for the paper's Shepp-Logan projections),
 cosine-weighted and Shepp-Logan filtered by the library's own filter.
+
+Workload slab4096: one GPU's share of a 4096^3 reconstruction, a mirror pair
+of 128-slice slabs at the volume's top and bottom (16 GiB), from 4096 views
+of 4096^2 pixels streamed in 16-view FP16 chunks: a producer stream
+generates the noisy 64-ellipsoid line integrals (noise 1%) on the slab's
+detector row bands only and filters them, while the back-projection of the
+previous chunk runs. A step is one pass over all 4096 views; GUPS counts
+the back-projection launches' event time (the rate the paper reports) and,
+beside it, the whole pipeline's wall time. The default run adds one such
+pass to its line (--no-slab skips it).
 """
 from __future__ import annotations
 
@@ -81,6 +91,8 @@ def parse():
     ap.add_argument("--no-16bit", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-slab", action="store_true",
+                    help="skip the streamed 4096^2-slab leg of the default run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB (a plain copy of known size, "
@@ -92,6 +104,109 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def slab_pass(g, cfg, ang, produce, vol, scale, timing_cls, reconstruct_slab, torch):
+    t = timing_cls()
+    sl = cfg["slab"]
+    reconstruct_slab(g, ang, produce, z0=sl["z0"], nz_local=sl["nz_local"], slab=sl["kind"],
+                     chunk=cfg["B"], dtype=torch.float16, kind=cfg["filter"], scale=scale,
+                     out=vol, timing=t)
+    return t
+
+
+def run_slab(steps, warmup, dev):
+    """Streamed slab reconstruction; returns (bp_ms, wall_ms, launches) per
+    pass (means over the timed passes) and the workload's geometry."""
+    import numpy as np
+    import torch
+
+    import paper_1909_02724_amd as fdk
+    import synth
+    import synth.gpu as sg
+    from paper_1909_02724_amd.pipeline import SlabTiming, reconstruct_slab
+
+    cfg = synth.config("slab4096")
+    g = cfg["geom"]
+    ang = synth.angles(cfg["np"])
+    sl = cfg["slab"]
+    ell = synth.ellipsoids(cfg["seed"], cfg["n_ell"], g)
+    ang_d = torch.as_tensor(ang, dtype=torch.float64, device=dev)
+    ell_d = torch.as_tensor(np.ascontiguousarray(ell).reshape(-1), dtype=torch.float64, device=dev)
+    sigma_d = sg.view_sigma(g, ang, ell, cfg["noise"], device=dev)
+    bands = fdk.slab_rows(g, ang, z0=sl["z0"], nz_local=sl["nz_local"], slab=sl["kind"])
+    log(f"slab4096: {g.nx}x{g.ny} x {sl['nz_local']} mirror-pair slab, {cfg['np']} views "
+        f"of {g.nv}x{g.nu} in FP16 chunks of {cfg['B']}; row bands {bands}")
+
+    def produce(view0, n, bands, e_bands):
+        for (v0, nr), e in zip(bands, e_bands):
+            sg.phantom_rows(g, ang_d[view0:view0 + n], ell_d, v0, e, view_index0=view0,
+                            seed=cfg["noise_seed"], sigma=sigma_d[view0:view0 + n])
+
+    scale = fdk.fdk_scale(g, ang)
+    vol = torch.empty((sl["nz_local"], g.ny, g.nx), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        slab_pass(g, cfg, ang, produce, vol, scale, SlabTiming, reconstruct_slab, torch)
+    torch.cuda.synchronize()
+    bp, wall = [], []
+    for k in range(steps):
+        t = slab_pass(g, cfg, ang, produce, vol, scale, SlabTiming, reconstruct_slab, torch)
+        bp.append(sum(t.bp_ms))
+        wall.append(t.wall_ms)
+        log(f"slab4096 pass {k}: back-projection {bp[-1]:.1f} ms over {len(t.bp_ms)} launches, "
+            f"pipeline {wall[-1]:.1f} ms")
+    n_launch = len(t.bp_ms)
+    del vol
+    torch.cuda.empty_cache()
+    return sum(bp) / len(bp), sum(wall) / len(wall), n_launch, g, cfg
+
+
+def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic):
+    per_launch_s = ms_step / 1e3 / launches
+    updates_per_launch = updates / launches
+    achieved = gups(updates_per_launch, per_launch_s)
+    valu_roof = N_CU * VALU_LANES_PER_CLK * CLOCK_HZ / VALU_OPS_PER_UPDATE / 2 ** 30
+    lds_roof = N_CU * LDS_BYTES_PER_CLK * CLOCK_HZ / LDS_BYTES_PER_UPDATE / 2 ** 30
+    peak = min(valu_roof, lds_roof)
+    nz = updates / (float(g.nx) * g.ny * views_per_launch * launches)
+    return {
+        "bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1), "unit": "GUPS",
+        "frac": round(achieved / peak, 4),
+        "traffic": None if traffic is None else round(traffic),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "kernel": kernel, "launches_per_step": launches,
+        "avg_launch_ms": round(per_launch_s * 1e3, 3),
+        "valu_roof_gups": round(valu_roof, 1), "lds_roof_gups": round(lds_roof, 1),
+        "hbm_algorithmic_bytes_per_launch": round(updates_per_launch * (
+            8.0 / views_per_launch + g.nu * g.nv * q_bytes / (g.nx * g.ny * nz))),
+    }
+
+
+def main_slab(args):
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bp_ms, wall_ms, launches, g, cfg = run_slab(args.steps, args.warmup, dev)
+    sl = cfg["slab"]
+    updates = float(g.nx) * g.ny * sl["nz_local"] * cfg["np"]
+    out = {
+        "metric": METRIC, "value": round(gups(updates, bp_ms / 1e3), 2), "unit": "GUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(bp_ms, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16",
+        "data": "synthetic: seeded 64-ellipsoid phantom with 1% Gaussian noise, generated and "
+                "Shepp-Logan filtered on the GPU per 16-view chunk on the slab's row bands",
+        "config": {"workload": f"slab4096: {g.nx}x{g.ny}x{sl['nz_local']} FP32 mirror-pair slab "
+                               f"of a {g.nz}^3 volume, {cfg['np']} views of {g.nv}x{g.nu} FP16 "
+                               f"in chunks of {cfg['B']}",
+                   "nx": g.nx, "ny": g.ny, "nz_local": sl["nz_local"], "n_views": cfg["np"],
+                   "nu": g.nu, "nv": g.nv, "views_per_launch": cfg["B"]},
+        "pipeline_gups": round(gups(updates, wall_ms / 1e3), 2),
+        "pipeline_ms_per_step": round(wall_ms, 2),
+        "roofline": roofline_of(bp_ms, launches, updates, g, cfg["B"], 2.0,
+                                "bp_tiled_mirror_kernel<f16_t>", None),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -99,6 +214,9 @@ def main():
               "(one GPU's share is the workload; see the design notes on sharding).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "slab4096":
+        return main_slab(args)
 
     import numpy as np
     import torch
@@ -192,24 +310,18 @@ def main():
         del x, qa
 
     # ---- roofline of the dominant kernel (the back-projection launches) ----
-    per_launch_s = ms32 / 1e3 / launches
-    updates_per_launch = updates / launches
-    achieved = gups(updates_per_launch, per_launch_s)
-    valu_roof = N_CU * VALU_LANES_PER_CLK * CLOCK_HZ / VALU_OPS_PER_UPDATE / 2 ** 30
-    lds_roof = N_CU * LDS_BYTES_PER_CLK * CLOCK_HZ / LDS_BYTES_PER_UPDATE / 2 ** 30
-    peak = min(valu_roof, lds_roof)
-    traffic = profiled_traffic(args.workload)
-    roofline = {
-        "bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1), "unit": "GUPS",
-        "frac": round(achieved / peak, 4),
-        "traffic": None if traffic is None else round(traffic),
-        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-        "kernel": "bp_tiled_mirror_kernel<float>", "launches_per_step": launches,
-        "avg_launch_ms": round(per_launch_s * 1e3, 3),
-        "valu_roof_gups": round(valu_roof, 1), "lds_roof_gups": round(lds_roof, 1),
-        "hbm_algorithmic_bytes_per_launch": round(updates_per_launch * (
-            8.0 / 32 + g.nu * g.nv * 4.0 / (g.nx * g.ny * g.nz))),
-    }
+    roofline = roofline_of(ms32, launches, updates, g, 32, 4.0, "bp_tiled_mirror_kernel<float>",
+                           profiled_traffic(args.workload))
+
+    if not args.no_slab and args.workload == "bp2048":
+        del q32
+        torch.cuda.empty_cache()
+        bp_ms, wall_ms, nl, gs, cs = run_slab(1, 0, dev)
+        su = float(gs.nx) * gs.ny * cs["slab"]["nz_local"] * cs["np"]
+        result_extra["slab4096_f16_gups"] = round(gups(su, bp_ms / 1e3), 2)
+        result_extra["slab4096_pipeline_gups"] = round(gups(su, wall_ms / 1e3), 2)
+        result_extra["slab4096_bp_ms"] = round(bp_ms, 1)
+        result_extra["slab4096_pipeline_ms"] = round(wall_ms, 1)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the workload ----
     cpu = None

@@ -146,6 +146,21 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
                                fdk_slab_kind slab, float* q, float scale,
                                uint32_t flags, void* stream);
 
+/* Detector rows that fdk_backproject reads for a slab (same z0, nz_local,
+ * slab as there), over all np views of the scan: the rows of the bilinear
+ * taps of every voxel of the slab (Alg. 3), plus one spare row on each side.
+ * Rows outside these bands never reach the slab, so a reconstruction that
+ * streams projections may filter (fdk_filter_rows) and keep only these.
+ * On success band = {v0_a, n_a, v0_b, n_b}: rows [v0_a, v0_a + n_a) and
+ * [v0_b, v0_b + n_b), ascending and disjoint, with n_b = 0 when one band
+ * covers the slab (a contiguous slab, or mirror halves whose bands touch)
+ * and n_a = 0 too when the slab projects off the detector. Host-only: no
+ * device work. band is a host array of 4 int32.
+ * Errors: as fdk_backproject for the geometry and slab; FDK_ERR_INVALID_ARG
+ * for a null band. */
+fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local,
+                         fdk_slab_kind slab, int32_t band[4]);
+
 /* pi * d^2 / Np: the FDK constant (1/2) * (2 pi / Np) * d^2 of a full
  * 360-degree scan, since W = 1/z^2 carries no d^2. Returns NaN for a null
  * or invalid geometry. */

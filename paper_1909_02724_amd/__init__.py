@@ -101,6 +101,8 @@ def lib():
         L.fdk_filter_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int,
                                       C.c_void_p]
+        L.fdk_slab_rows.restype = C.c_int
+        L.fdk_slab_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int, C.POINTER(C.c_int32)]
         L.fdk_fdk_scale.restype = C.c_double
         L.fdk_fdk_scale.argtypes = [P]
         L.fdk_last_error.restype = C.c_char_p
@@ -216,6 +218,17 @@ def filter(e: torch.Tensor, geom, angles, *, view0: int = 0, kind: str = "ramlak
                                  out.stride(0) if out.shape[0] > 1 else nrows * geom.nu,
                                  _DTYPES[out.dtype], _FILTERS[kind], _stream(e)))
     return out
+
+
+def slab_rows(geom, angles, *, z0: int = 0, nz_local: int | None = None,
+              slab: str = "contiguous") -> list[tuple[int, int]]:
+    """Detector row bands [(v0, nrows), ...] (at most two, ascending) that
+    the back-projection of this slab reads over all views of the scan."""
+    z0, nzl, sk = _slab(geom, z0, nz_local, slab)
+    cg, _keep = _cgeom(geom, angles)
+    band = (C.c_int32 * 4)()
+    _check(lib().fdk_slab_rows(C.byref(cg), z0, nzl, sk, band))
+    return [(band[2 * n], band[2 * n + 1]) for n in range(2) if band[2 * n + 1] > 0]
 
 
 def fdk_scale(geom, angles) -> float:

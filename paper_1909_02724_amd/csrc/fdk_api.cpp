@@ -2,10 +2,12 @@
 // validation, per-view FP64 geometry, slab decomposition into slice runs
 // and kernel dispatch on the caller's stream. Nothing here touches the HIP
 // runtime until every argument has been validated.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "fdk_internal.h"
@@ -298,6 +300,73 @@ fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews,
   if (int err = fdk::launch_filter(gc, g->du, g->dv, g->sod, g->sdd, rb, e, q, out_dtype, kind,
                                    stream))
     return fail(FDK_ERR_HIP, "filter launch failed: HIP error %d", err);
+  return ok();
+}
+
+fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local, fdk_slab_kind slab,
+                         int32_t band[4]) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if (!band) return fail(FDK_ERR_INVALID_ARG, "band pointer is NULL");
+  const fdk::GeoConst gc = make_geo(g);
+  Slab sl;
+  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  // Global slice intervals the slab holds.
+  int32_t iv[2][2];
+  int niv = 1;
+  if (slab == FDK_SLAB_CONTIGUOUS) {
+    iv[0][0] = z0;
+    iv[0][1] = z0 + nz_local - 1;
+  } else {
+    const int32_t h = nz_local / 2;
+    iv[0][0] = z0;
+    iv[0][1] = z0 + h - 1;
+    iv[1][0] = g->nz - z0 - h;
+    iv[1][1] = g->nz - z0 - 1;
+    niv = 2;
+  }
+  // v(k) = cv + kv (k - cz) / z is monotone in k and in 1/z, and z is affine
+  // in (i, j), so each view's extremes sit at the slab's end slices and the
+  // volume's corner columns. Taps reach floor(v) + 1; one spare row on each
+  // side covers the kernels' FP32 rounding of v.
+  int32_t lo[2], hi[2];
+  for (int n = 0; n < niv; ++n) {
+    double vmin = INFINITY, vmax = -INFINITY;
+    for (int32_t s = 0; s < g->np; ++s) {
+      const fdk::ViewGeo vg = make_view(g, g->angles[s]);
+      double zmin = INFINITY, zmax = -INFINITY;
+      for (int ci = 0; ci < 2; ++ci)
+        for (int cj = 0; cj < 2; ++cj) {
+          const double z = vg.c0 + vg.ci * (ci ? g->nx - 1 : 0) + vg.cj * (cj ? g->ny - 1 : 0);
+          zmin = std::fmin(zmin, z);
+          zmax = std::fmax(zmax, z);
+        }
+      for (int e = 0; e < 2; ++e) {
+        const double dk = iv[n][e] - gc.cz;
+        for (double z : {zmin, zmax}) {
+          const double v = gc.cv + gc.kv * dk / z;
+          vmin = std::fmin(vmin, v);
+          vmax = std::fmax(vmax, v);
+        }
+      }
+    }
+    lo[n] = static_cast<int32_t>(std::max(0.0, std::floor(vmin) - 1.0));
+    hi[n] = static_cast<int32_t>(std::min<double>(g->nv - 1, std::floor(vmax) + 2.0));
+  }
+  // Non-empty intervals in ascending order, merged where they touch.
+  std::vector<std::pair<int32_t, int32_t>> rows;
+  for (int n = 0; n < niv; ++n)
+    if (lo[n] <= hi[n]) rows.emplace_back(lo[n], hi[n]);
+  std::sort(rows.begin(), rows.end());
+  if (rows.size() == 2 && rows[1].first <= rows[0].second + 1) {
+    rows[0].second = std::max(rows[0].second, rows[1].second);
+    rows.pop_back();
+  }
+  band[0] = band[1] = band[2] = band[3] = 0;
+  for (size_t n = 0; n < rows.size(); ++n) {
+    band[2 * n] = rows[n].first;
+    band[2 * n + 1] = rows[n].second - rows[n].first + 1;
+  }
   return ok();
 }
 

@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "Geom", "CONFIGS", "config", "angles", "ellipsoids", "ball",
-    "sample_voxels", "random_projections",
+    "sample_voxels", "random_projections", "normal_draws",
 ]
 
 
@@ -79,7 +79,7 @@ CONFIGS = {
     # mirror pair of 128-slice slabs, 4096 views of 4096^2 in FP16, 16-view chunks.
     "slab4096": dict(geom=_cube(4096, 4096), np=4096, n_ell=64, seed=104, filter="shepp-logan",
                      dtype="f16", B=16, slab=dict(kind="mirror_pair", z0=0, nz_local=256),
-                     noise=0.01),
+                     noise=0.01, noise_seed=204),
     # Differentiable: batch of 4 volumes of 256^3, 360 views of 384^2; the
     # whole volume lies inside the field of view (192 px >= 181 half-diagonal).
     "diff256": dict(geom=Geom(nx=256, ny=256, nz=256, nu=384, nv=384, sod=2000.0, sdd=4000.0),
@@ -180,3 +180,33 @@ def random_projections(seed: int, n_views: int, geom: Geom, smooth: bool = False
             img += rng.uniform(0.1, 1.0) * np.sqrt(np.clip(1.0 - r2, 0.0, None))
         out[s] = img
     return out
+
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+
+
+def _splitmix64(seed: int, counters: np.ndarray) -> np.ndarray:
+    """SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) output number c + 1
+    of the stream started at `seed`, for each counter c (uint64 arrays)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (counters + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def normal_draws(seed: int, geom: Geom, views, rows, cols) -> np.ndarray:
+    """Standard normal draws keyed (seed, view, row, column), the noise of
+    the noisy-phantom workload: pixel counter m = (view Nv + row) Nu + col,
+    Box-Muller (Box and Muller, 1958) on SplitMix64 draws 2m and 2m + 1 with
+    u1 = (top 53 bits + 1) 2^-53 in (0, 1] and u2 = (top 53 bits) 2^-53.
+    Arguments broadcast against each other."""
+    v, r, c = np.broadcast_arrays(np.asarray(views, np.uint64), np.asarray(rows, np.uint64),
+                                  np.asarray(cols, np.uint64))
+    with np.errstate(over="ignore"):
+        m = (v * np.uint64(geom.nv) + r) * np.uint64(geom.nu) + c
+        x1 = _splitmix64(seed, np.uint64(2) * m)
+        x2 = _splitmix64(seed, np.uint64(2) * m + np.uint64(1))
+    u1 = ((x1 >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+    u2 = (x2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)

@@ -6,6 +6,11 @@
 //    values from its own implementation of the published generator.
 //  - synth_phantom_project: analytic line integrals of a sum of ellipsoids
 //    along the ray from the source to every detector pixel centre (FP64).
+//  - synth_phantom_rows: the same on a band of detector rows, plus additive
+//    Gaussian noise keyed by (seed, view, row, column): two SplitMix64 draws
+//    through the Box-Muller transform (Box and Muller, 1958).
+//  - synth_view_sigma: per-view noise level, a fraction of the largest
+//    clean line integral on the detector row through the principal point.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -51,15 +56,11 @@ struct ScanGeom {
 };
 
 // Ellipsoid record: centre (3), semi-axes (3), rotation (3x3 row-major,
-// columns are the axes in world coordinates), density.
-__global__ void phantom_project_kernel(ScanGeom g, const double* __restrict__ angles,
-                                       int32_t nviews, const double* __restrict__ ell,
-                                       int32_t nell, float* __restrict__ out) {
-  const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t b = blockIdx.y;
-  const int32_t s = blockIdx.z;
-  if (a >= g.nu || b >= g.nv || s >= nviews) return;
-  const double beta = angles[s];
+// columns are the axes in world coordinates), density. Line integral along
+// the ray from the source to the centre of pixel (a, b) of the view at
+// gantry angle beta.
+__device__ double ray_integral(const ScanGeom& g, double beta, double a, double b,
+                               const double* __restrict__ ell, int32_t nell) {
   const double cb = cos(beta), sb = sin(beta);
   // Source at the gantry origin; pixel (a, b) on the plane at distance D.
   const double src[3] = {-g.sod * sb, -g.sod * cb, 0.0};
@@ -83,7 +84,64 @@ __global__ void phantom_project_kernel(ScanGeom g, const double* __restrict__ an
     const double disc = B * B - A * Cc;
     if (disc > 0.0) acc += e[15] * (2.0 * sqrt(disc) / A) * len;
   }
-  out[(static_cast<int64_t>(s) * g.nv + b) * g.nu + a] = static_cast<float>(acc);
+  return acc;
+}
+
+__global__ void phantom_project_kernel(ScanGeom g, const double* __restrict__ angles,
+                                       int32_t nviews, const double* __restrict__ ell,
+                                       int32_t nell, float* __restrict__ out) {
+  const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t b = blockIdx.y;
+  const int32_t s = blockIdx.z;
+  if (a >= g.nu || b >= g.nv || s >= nviews) return;
+  out[(static_cast<int64_t>(s) * g.nv + b) * g.nu + a] =
+      static_cast<float>(ray_integral(g, angles[s], a, b, ell, nell));
+}
+
+// Standard normal for pixel counter m: Box-Muller on the draws 2m and
+// 2m + 1, with u1 = (top 53 bits + 1) 2^-53 in (0, 1] and u2 = (top 53
+// bits) 2^-53 in [0, 1).
+__device__ double normal_draw(uint64_t seed, uint64_t m) {
+  const double u1 = static_cast<double>((splitmix64(seed, 2u * m) >> 11) + 1u) * 0x1p-53;
+  const double u2 = static_cast<double>(splitmix64(seed, 2u * m + 1u) >> 11) * 0x1p-53;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+__global__ void phantom_rows_kernel(ScanGeom g, const double* __restrict__ angles, int32_t v0,
+                                    const double* __restrict__ ell, int32_t nell,
+                                    uint64_t seed, int64_t view_index0,
+                                    const double* __restrict__ sigma, float* __restrict__ out,
+                                    int64_t vstride) {
+  const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t r = blockIdx.y;
+  const int32_t s = blockIdx.z;
+  if (a >= g.nu) return;
+  const int32_t b = v0 + r;
+  double e = ray_integral(g, angles[s], a, b, ell, nell);
+  if (sigma) {
+    const uint64_t m = (static_cast<uint64_t>(view_index0 + s) * g.nv + b) * g.nu + a;
+    e += sigma[s] * normal_draw(seed, m);
+  }
+  out[s * vstride + static_cast<int64_t>(r) * g.nu + a] = static_cast<float>(e);
+}
+
+__global__ void view_sigma_kernel(ScanGeom g, const double* __restrict__ angles,
+                                  const double* __restrict__ ell, int32_t nell, double rel,
+                                  double* __restrict__ sigma) {
+  __shared__ double red[256];
+  const int32_t s = blockIdx.x;
+  const double row = floor(g.cv);
+  double m = 0.0;
+  for (int32_t a = threadIdx.x; a < g.nu; a += blockDim.x)
+    m = fmax(m, ray_integral(g, angles[s], a, row, ell, nell));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int32_t w = blockDim.x / 2; w > 0; w /= 2) {
+    if (static_cast<int32_t>(threadIdx.x) < w)
+      red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[s] = rel * red[0];
 }
 
 }  // namespace
@@ -113,6 +171,41 @@ int synth_phantom_project(int32_t nu, int32_t nv, double du, double dv, double o
   dim3 grid((nu + 63) / 64, nv, nviews);
   hipLaunchKernelGGL(phantom_project_kernel, grid, dim3(64), 0, static_cast<hipStream_t>(stream),
                      g, angles, nviews, ell, nell, out);
+  return static_cast<int>(hipGetLastError());
+}
+
+// Rows [v0, v0 + nrows) of views view_index0 + s (s < nviews; angles holds
+// those views' angles): out[s * out_view_stride + r * nu + a] = line
+// integral + sigma[s] * N(seed; view, row, column). sigma may be NULL (no
+// noise). All arrays are device memory.
+int synth_phantom_rows(int32_t nu, int32_t nv, double du, double dv, double off_u, double off_v,
+                       double sod, double sdd, const double* angles, int32_t nviews, int32_t v0,
+                       int32_t nrows, const double* ell, int32_t nell, uint64_t seed,
+                       int64_t view_index0, const double* sigma, float* out,
+                       int64_t out_view_stride, void* stream) {
+  if (nu <= 0 || nv <= 0 || nviews < 0 || nrows < 0 || v0 < 0 || v0 + nrows > nv || nell < 0 ||
+      !angles || !out || (nell && !ell) || view_index0 < 0 ||
+      out_view_stride < static_cast<int64_t>(nrows) * nu)
+    return static_cast<int>(hipErrorInvalidValue);
+  if (nviews == 0 || nrows == 0) return 0;
+  ScanGeom g{nu, nv, du, dv, 0.5 * (nu - 1) + off_u, 0.5 * (nv - 1) + off_v, sod, sdd};
+  dim3 grid((nu + 63) / 64, nrows, nviews);
+  hipLaunchKernelGGL(phantom_rows_kernel, grid, dim3(64), 0, static_cast<hipStream_t>(stream), g,
+                     angles, v0, ell, nell, seed, view_index0, sigma, out, out_view_stride);
+  return static_cast<int>(hipGetLastError());
+}
+
+// sigma[s] = rel * max over columns of the clean line integral on row
+// floor(cv) of view s (cv = (nv - 1) / 2 + off_v).
+int synth_view_sigma(int32_t nu, int32_t nv, double du, double dv, double off_u, double off_v,
+                     double sod, double sdd, const double* angles, int32_t nviews,
+                     const double* ell, int32_t nell, double rel, double* sigma, void* stream) {
+  if (nu <= 0 || nv <= 0 || nviews < 0 || nell < 0 || !angles || !sigma || (nell && !ell))
+    return static_cast<int>(hipErrorInvalidValue);
+  if (nviews == 0) return 0;
+  ScanGeom g{nu, nv, du, dv, 0.5 * (nu - 1) + off_u, 0.5 * (nv - 1) + off_v, sod, sdd};
+  hipLaunchKernelGGL(view_sigma_kernel, dim3(nviews), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), g, angles, ell, nell, rel, sigma);
   return static_cast<int>(hipGetLastError());
 }
 

@@ -1,8 +1,9 @@
 """GPU-side synthetic inputs (benchmark and test infrastructure).
 
 ctypes over synth/libsynth_gpu.so (built from synth/gpu.hip): SplitMix64
-counter-based values written straight into device memory, and an analytic
-ellipsoid-phantom projector. Neither holds any reconstruction arithmetic.
+counter-based values written straight into device memory, an analytic
+ellipsoid-phantom projector (whole views or a band of rows) and counter-keyed
+Gaussian noise. None of it holds any reconstruction arithmetic.
 """
 from __future__ import annotations
 
@@ -43,6 +44,13 @@ def lib():
         L.synth_phantom_project.restype = C.c_int
         L.synth_phantom_project.argtypes = [C.c_int32, C.c_int32] + [C.c_double] * 6 + [
             C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.synth_phantom_rows.restype = C.c_int
+        L.synth_phantom_rows.argtypes = [C.c_int32, C.c_int32] + [C.c_double] * 6 + [
+            C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_uint64,
+            C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.synth_view_sigma.restype = C.c_int
+        L.synth_view_sigma.argtypes = [C.c_int32, C.c_int32] + [C.c_double] * 6 + [
+            C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -75,4 +83,47 @@ def phantom_project(geom, angles, ell, out: torch.Tensor | None = None,
                                      C.c_void_p(out.data_ptr()), _stream(out))
     if rc:
         raise RuntimeError(f"synth_phantom_project: HIP error {rc}")
+    return out
+
+
+def _geo_args(geom):
+    return (geom.nu, geom.nv, geom.du, geom.dv, geom.off_u, geom.off_v, geom.sod, geom.sdd)
+
+
+def view_sigma(geom, angles, ell, rel: float, device="cuda") -> torch.Tensor:
+    """Noise level per view (float64, device): rel times the largest clean
+    line integral on the detector row floor(cv) through the principal point."""
+    ang = torch.as_tensor(np.asarray(angles, np.float64), device=device)
+    e = torch.as_tensor(np.ascontiguousarray(ell, np.float64).reshape(-1), device=device)
+    out = torch.empty(ang.numel(), dtype=torch.float64, device=device)
+    rc = lib().synth_view_sigma(*_geo_args(geom), C.c_void_p(ang.data_ptr()), ang.numel(),
+                                C.c_void_p(e.data_ptr()), e.numel() // 16, float(rel),
+                                C.c_void_p(out.data_ptr()), _stream(out))
+    if rc:
+        raise RuntimeError(f"synth_view_sigma: HIP error {rc}")
+    return out
+
+
+def phantom_rows(geom, angles: torch.Tensor, ell: torch.Tensor, v0: int, out: torch.Tensor,
+                 view_index0: int = 0, seed: int = 0,
+                 sigma: torch.Tensor | None = None) -> torch.Tensor:
+    """Rows [v0, v0 + out.shape[1]) of the views whose angles are `angles`
+    (device float64; global view numbers view_index0 + s) into `out`
+    (float32 (nviews, nrows, Nu), rows contiguous, any view stride): line
+    integrals plus sigma[s] * standard normal keyed (seed, view, row, column)."""
+    n, nrows = out.shape[0], out.shape[1]
+    assert out.is_cuda and out.dtype == torch.float32 and out.shape[2] == geom.nu
+    assert out.stride(2) == 1 and (nrows <= 1 or out.stride(1) == geom.nu)
+    assert angles.is_cuda and angles.dtype == torch.float64 and angles.numel() == n
+    assert ell.is_cuda and ell.dtype == torch.float64
+    if sigma is not None:
+        assert sigma.is_cuda and sigma.dtype == torch.float64 and sigma.numel() == n
+    vstride = out.stride(0) if n > 1 else nrows * geom.nu
+    rc = lib().synth_phantom_rows(*_geo_args(geom), C.c_void_p(angles.data_ptr()), n, int(v0),
+                                  nrows, C.c_void_p(ell.data_ptr()), ell.numel() // 16,
+                                  int(seed), int(view_index0),
+                                  None if sigma is None else C.c_void_p(sigma.data_ptr()),
+                                  C.c_void_p(out.data_ptr()), vstride, _stream(out))
+    if rc:
+        raise RuntimeError(f"synth_phantom_rows: HIP error {rc}")
     return out

@@ -135,3 +135,57 @@ def test_python_layer_refuses_cpu_tensors():
     import torch
     with pytest.raises(ValueError, match="GPU tensor"):
         fdk.backproject(torch.zeros(4, 20, 24), GOOD, ANG)
+
+
+def _tap_rows(g, ang, ks):
+    """Rows of every bilinear tap of every voxel with global slice in ks, by
+    the oracle's projection matrices (Eq. 2, Alg. 3)."""
+    import oracle
+    ii, jj, kk = np.meshgrid(np.arange(g.nx), np.arange(g.ny), np.asarray(ks), indexing="ij")
+    h = np.stack([ii.ravel(), jj.ravel(), kk.ravel(), np.ones(ii.size)], 0).astype(np.float64)
+    rows = set()
+    for beta in ang:
+        x, y, z = oracle.projection_matrix(g, beta) @ h
+        nv = np.floor(y / z).astype(np.int64)
+        rows.update(np.unique(nv).tolist())
+        rows.update(np.unique(nv + 1).tolist())
+    return {r for r in rows if 0 <= r < g.nv}
+
+
+@pytest.mark.parametrize("slab, z0, nzl", [("contiguous", 0, 20), ("contiguous", 11, 6),
+                                           ("contiguous", 0, 40), ("mirror_pair", 0, 8),
+                                           ("mirror_pair", 9, 20), ("mirror_pair", 3, 2)])
+def test_slab_rows_cover_every_tap(slab, z0, nzl):
+    """The bands hold every row any voxel of the slab taps, in every view,
+    and little else (one spare row a side plus the spread over views)."""
+    import synth
+    g = synth.Geom(nx=24, ny=20, nz=40, nu=48, nv=60, sod=90.0, sdd=200.0, du=1.5, dv=1.5)
+    ang = synth.angles(24, start=0.05)
+    if slab == "contiguous":
+        ks = np.arange(z0, z0 + nzl)
+    else:
+        h = nzl // 2
+        ks = np.concatenate([np.arange(z0, z0 + h), np.arange(g.nz - z0 - h, g.nz - z0)])
+    bands = fdk.slab_rows(g, ang, z0=z0, nz_local=nzl, slab=slab)
+    held = set()
+    for v0, n in bands:
+        assert 0 <= v0 and v0 + n <= g.nv and n > 0
+        held.update(range(v0, v0 + n))
+    need = _tap_rows(g, ang, ks)
+    assert need <= held, sorted(need - held)
+    # no more than two spare rows per band edge beyond the taps' extent
+    assert len(held) <= len(need) + 4 * len(bands)
+    if len(bands) == 2:
+        assert bands[0][0] + bands[0][1] < bands[1][0]
+
+
+def test_slab_rows_validation():
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    L = fdk.lib()
+    band = (C.c_int32 * 4)()
+    assert L.fdk_slab_rows(C.byref(cg), 0, 8, 0, None) == 1
+    assert "band" in L.fdk_last_error().decode()
+    assert L.fdk_slab_rows(C.byref(cg), 4, 8, 0, band) == 1
+    assert L.fdk_slab_rows(C.byref(cg), 0, 5, 1, band) == 1
+    assert L.fdk_slab_rows(C.byref(cg), 0, 8, 0, band) == 0
+    assert band[1] > 0
