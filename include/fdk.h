@@ -35,6 +35,13 @@
 
 #include <stdint.h>
 
+/* Exported entry points (the library hides every other symbol). */
+#if defined(__GNUC__) || defined(__clang__)
+#define FDK_API __attribute__((visibility("default")))
+#else
+#define FDK_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -92,7 +99,7 @@ typedef struct {
  * is fdk_backproject's `scale`), which keeps 16-bit storage in range.
  * Errors: FDK_ERR_INVALID_ARG for a bad geometry, range or null pointer;
  * FDK_ERR_UNSUPPORTED for an unknown kind or dtype, or Nu above 8192. */
-fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews,
+FDK_API fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews,
                       const float* e, void* q, fdk_dtype out_dtype,
                       fdk_filter_kind kind, void* stream);
 
@@ -105,7 +112,7 @@ fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews,
  * only the rows a volume slab projects to.
  * Errors: as fdk_filter, plus FDK_ERR_INVALID_ARG for a band outside
  * [0, Nv) or a view stride smaller than nrows * Nu. */
-fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
+FDK_API fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
                            int32_t nrows, const float* e, int64_t e_view_stride, void* q,
                            int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
                            void* stream);
@@ -125,7 +132,7 @@ fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews,
  * range outside [0, np), slab outside the volume (or an odd nz_local /
  * overlapping halves for a mirror pair), sod not larger than the volume's
  * half-diagonal in x-y (some z <= 0, Eq. 3), sdd <= 0, or a non-finite value. */
-fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
+FDK_API fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
                            const void* q, fdk_dtype q_dtype, float* vol,
                            int32_t z0, int32_t nz_local, fdk_slab_kind slab,
                            float scale, uint32_t flags, void* stream);
@@ -141,7 +148,7 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
  * brick and view so that no partial sum can overflow; the workgroups' sums
  * meet in FP32 atomics, so the last bits vary from run to run.
  * Errors: as fdk_backproject. */
-fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nviews,
+FDK_API fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nviews,
                                const float* vol, int32_t z0, int32_t nz_local,
                                fdk_slab_kind slab, float* q, float scale,
                                uint32_t flags, void* stream);
@@ -158,17 +165,17 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
  * device work. band is a host array of 4 int32.
  * Errors: as fdk_backproject for the geometry and slab; FDK_ERR_INVALID_ARG
  * for a null band. */
-fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local,
+FDK_API fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local,
                          fdk_slab_kind slab, int32_t band[4]);
 
 /* pi * d^2 / Np: the FDK constant (1/2) * (2 pi / Np) * d^2 of a full
  * 360-degree scan, since W = 1/z^2 carries no d^2. Returns NaN for a null
  * or invalid geometry. */
-double fdk_fdk_scale(const fdk_geometry* g);
+FDK_API double fdk_fdk_scale(const fdk_geometry* g);
 
 /* Message describing the calling thread's most recent failed call ("" if
  * none). Valid until that thread's next call into the library. */
-const char* fdk_last_error(void);
+FDK_API const char* fdk_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -240,49 +240,65 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     // detector skip the range checks.
     auto load_stage = [&](int32_t s0, int32_t nvc) {
       int32_t sl = 0, rr = 0;
-      __amdgpu_buffer_rsrc_t rsrc;
       int32_t org_v = 0, inside = 0;
-      uint32_t c0 = 0, c1 = 0;
+      uint32_t c0 = 0, c1 = 0, off = 0, offm = 0;
+      const uint32_t step = static_cast<uint32_t>(rstep) * row_es;
 #pragma unroll
       for (int m = 0; m < kPrefetchSlots; ++m) {
         if (sl < nvc) {
+          // The descriptor is rebuilt per slot (scalar work): carried across
+          // slots, the compiler moves it to vector registers and wraps each
+          // load in a loop over lanes.
+          const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+              const_cast<T*>(q + (s0 + sl) * vstride), 0, nrec, kBufferWord3);
           if (rr == 0) {  // uniform: new view
             const int32_t s = s0 + sl;
-            rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(q + s * vstride), 0, nrec,
-                                                     kBufferWord3);
             const int32_t gu = bvs[s].org_u + sc;
             org_v = bvs[s].org_v;
-            inside = bvs[s].inside;
+            inside = __builtin_amdgcn_readfirstlane(bvs[s].inside);
             c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
                      ? static_cast<uint32_t>(gu) * es : kBadCol;
             c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
                      ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
+            off = static_cast<uint32_t>(org_v + sr) * row_es + c0;
+            offm = static_cast<uint32_t>(gc.mirror_g - org_v - sr) * row_es + c0;
           }
+          // Only the offsets depend on the branch: the loads themselves are
+          // issued in common code, unconditionally (uniform control flow),
+          // so nothing waits for them until the tile is written. A lane with
+          // no row here reads at an out-of-range offset, which returns zero
+          // without a fetch. Views whose tile lies on the detector just step
+          // the row offsets.
           const int32_t r = sr + rr * rstep;
-          if (stager && r < tv) {
-            const int32_t gr = org_v + r;
-            const int32_t gm = gc.mirror_g - gr;
-            uint32_t ro, rm;
-            if (inside) {
-              ro = __umul24(static_cast<uint32_t>(gr), row_es);
-              rm = __umul24(static_cast<uint32_t>(gm), row_es);
-            } else {
-              ro = static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
-                       ? __umul24(static_cast<uint32_t>(gr), row_es) : kBadRow;
-              rm = static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
-                       ? __umul24(static_cast<uint32_t>(gm), row_es) : kBadRow;
-            }
-            uint4 p;
-            p.x = buf_load_raw<T>(rsrc, ro + c0);
-            p.y = buf_load_raw<T>(rsrc, ro + c1);
-            if (MIRROR) {
-              p.z = buf_load_raw<T>(rsrc, rm + c0);
-              p.w = buf_load_raw<T>(rsrc, rm + c1);
-            } else {
-              p.z = p.w = 0u;
-            }
-            pre[m] = p;
+          const bool on = stager && r < tv;
+          uint32_t o0, o1, m0, m1;
+          if (inside) {
+            o0 = on ? off : kBadRow;
+            o1 = o0 + es;
+            m0 = on ? offm : kBadRow;
+            m1 = m0 + es;
+          } else {
+            const int32_t gr = org_v + r, gm = gc.mirror_g - gr;
+            const uint32_t ro = on && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
+                                    ? __umul24(static_cast<uint32_t>(gr), row_es) : kBadRow;
+            const uint32_t rm = on && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
+                                    ? __umul24(static_cast<uint32_t>(gm), row_es) : kBadRow;
+            o0 = ro + c0;
+            o1 = ro + c1;
+            m0 = rm + c0;
+            m1 = rm + c1;
           }
+          uint4 p;
+          p.x = buf_load_raw<T>(rsrc, o0);
+          p.y = buf_load_raw<T>(rsrc, o1);
+          if (MIRROR) {
+            p.z = buf_load_raw<T>(rsrc, m0);
+            p.w = buf_load_raw<T>(rsrc, m1);
+          }
+          if (!MIRROR) p.z = p.w = 0u;
+          pre[m] = p;
+          off += step;
+          offm -= step;
         }
         if (++rr == rows) {
           rr = 0;
@@ -290,8 +306,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
         }
       }
     };
-    // Write pre[] as tile entries: entry (r, c) of slot sl at
-    // sl * tu * tvp + c * tvp + r.
+
     auto store_stage = [&](int32_t nvc) {
       int32_t sl = 0, rr = 0;
 #pragma unroll
@@ -322,9 +337,12 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
       for (int32_t sl = 0; sl < nvc; ++sl) {
         const ColumnF32 c = column_f32(bvs[s0 + sl], txf, tyf, kvf);
         const uint32_t nu = min(c.nu, static_cast<uint32_t>(tu - 1));
-        const uint32_t base =
-            static_cast<uint32_t>(sl * slot_entries) + nu * static_cast<uint32_t>(tvp) + c.nvb;
-        const char* pb = tile_bytes + base * kTileEntryBytes;
+        // One register holds the column's tile offset, so each pair's
+        // address is a single shift-and-add.
+        uint32_t cbase = (static_cast<uint32_t>(sl * slot_entries) +
+                          nu * static_cast<uint32_t>(tvp) + c.nvb) * kTileEntryBytes;
+        asm volatile("" : "+v"(cbase));
+        const char* pb = tile_bytes + cbase;
         // Reads run one voxel pair ahead of use, so LDS latency overlaps the
         // previous pair's arithmetic.
         uint32_t dn;

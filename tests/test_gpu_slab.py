@@ -94,7 +94,11 @@ def test_noisy_rows_and_sigma_match_oracle():
         ell = synth.ellipsoids(7, 6, g)
         sig_ref = oracle_sigma(g, ang, ell, 0.01)
         sig = sg.view_sigma(g, ang, ell, 0.01, device=DEV).cpu().numpy()
-        assert np.allclose(sig, sig_ref, rtol=1e-12, atol=0)
+        # two FP64 ray tracers written independently: near-tangent chords
+        # amplify last-bit differences in the ray direction
+        rd = float(np.max(np.abs(sig - sig_ref) / sig_ref))
+        announce(f"view sigma nu={g.nu}: max relative difference {rd:.2e}")
+        assert rd <= 1e-8
         v0, nr = g.nv // 3, 5
         e = torch.empty((6, nr, g.nu), dtype=torch.float32, device=DEV)
         produce, sigma_d = synth_producer(g, ang, ell, 77, 0.01)
