@@ -417,11 +417,10 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   }
 }
 
-// Occupancy of the mirrored tiled variant is set by LDS (three 256-thread
-// workgroups per CU, three waves per SIMD), which leaves up to 168 VGPRs
-// per lane for the prefetched tile entries.
+// The mirrored tiled variant runs four 256-thread workgroups per CU (four
+// waves per SIMD): its LDS tiles fit 36 KB and it is held to 128 VGPRs.
 template <typename T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 3)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
                             const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
                             float scale, int accumulate) {
