@@ -117,7 +117,8 @@ def test_noisy_rows_and_sigma_match_oracle():
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
 def test_streamed_slab_matches_oracle(slab, z0, nzl, dtype):
     """Every voxel of a small slab from 40 views streamed in chunks of 16
-    (the last one ragged), rows outside the slab's bands never produced."""
+    (the last one ragged) and back-projected in launches of up to 32 views
+    (32 + 8), rows outside the slab's bands never produced."""
     g = SMALL
     n = 40
     ang = synth.angles(n, start=0.2)
@@ -127,7 +128,7 @@ def test_streamed_slab_matches_oracle(slab, z0, nzl, dtype):
     produce, _ = synth_producer(g, ang, ell, seed, rel)
     announce(f"streamed slab {slab} z0={z0} nz_local={nzl} {dtype}")
     vol = reconstruct_slab(g, ang, produce, z0=z0, nz_local=nzl, slab=slab, chunk=16,
-                           dtype=dtype, kind="shepp-logan", scale=scale, device=DEV)
+                           batch=32, dtype=dtype, kind="shepp-logan", scale=scale, device=DEV)
     torch.cuda.synchronize()
     sig = oracle_sigma(g, ang, ell, rel)
     rows = [(s, v) for s in range(n) for v in range(g.nv)]
@@ -207,9 +208,10 @@ def test_slab4096_streamed_pipeline_sampled():
 
 @pytest.mark.slow
 def test_slab4096_all_views_hash_sampled():
-    """Back-projection at the slab's full shape: all 4096 views in 16-view
-    FP16 chunks (the launch configuration the slab benchmark times), with
-    SplitMix64 values both sides regenerate, on sampled voxels."""
+    """Back-projection at the slab's full shape: all 4096 views, FP16, 32
+    views per launch (the launch configuration the slab benchmark times:
+    two 16-view chunks per launch), with SplitMix64 values both sides
+    regenerate, on sampled voxels."""
     import synth.gpu as sg
     c = synth.config("slab4096")
     g = c["geom"]
@@ -217,10 +219,10 @@ def test_slab4096_all_views_hash_sampled():
     ang = synth.angles(n)
     sl = c["slab"]
     seed = 4096
-    B = c["B"]
+    B = 32  # views per launch
     vol = torch.empty((sl["nz_local"], g.ny, g.nx), dtype=torch.float32, device=DEV)
     qc = torch.empty((B, g.nv, g.nu), dtype=torch.float16, device=DEV)
-    announce("slab4096: 256 chunks of hashed FP16 views into the 16 GiB slab")
+    announce("slab4096: 128 launches of 32 hashed FP16 views into the 16 GiB slab")
     for view0 in range(0, n, B):
         sg.hash_fill(qc, seed, counter0=view0 * g.nv * g.nu)
         fdk.backproject(qc, g, ang, view0=view0, out=vol, z0=sl["z0"], nz_local=sl["nz_local"],
@@ -248,9 +250,15 @@ def test_reconstruct_slab_timing_and_empty():
     produce, _ = synth_producer(g, ang, synth.ellipsoids(3, 4, g), 5, 0.0)
     t = SlabTiming()
     vol = reconstruct_slab(g, ang, produce, z0=2, nz_local=6, slab="mirror_pair", chunk=8,
-                           dtype=torch.float32, scale=1.0, device=DEV, timing=t)
+                           batch=8, dtype=torch.float32, scale=1.0, device=DEV, timing=t)
     assert len(t.bp_ms) == 3 and all(x > 0 for x in t.bp_ms) and t.wall_ms >= sum(t.bp_ms) * 0.5
     assert float(vol.abs().max()) > 0
+    # gathering chunks into launches of up to 16 views changes only rounding
+    t2 = SlabTiming()
+    vol16 = reconstruct_slab(g, ang, produce, z0=2, nz_local=6, slab="mirror_pair", chunk=8,
+                             batch=16, dtype=torch.float32, scale=1.0, device=DEV, timing=t2)
+    assert len(t2.bp_ms) == 2
+    assert rel_l2(vol16.double().cpu().numpy(), vol.double().cpu().numpy()) <= 1e-6
     # no chunks: the slab is zero
     vol2 = reconstruct_slab(g, ang, produce, z0=2, nz_local=6, slab="mirror_pair", chunk=8,
                             chunks=[], out=vol, device=DEV)
