@@ -460,11 +460,11 @@ __global__ __launch_bounds__(kThreads) void bp_direct_kernel(GeoConst gc, SliceR
 // tiled variant, FP64 columns for the direct one), so each is the transpose
 // of its back-projector up to rounding.
 //
-// Tiled variant: per view, the brick's splats accumulate in an LDS tile with
+// Tiled variant: per view, the brick's splats accumulate in LDS tiles with
 // the back-projector's transposed layout (one more column, for the u + 1
-// taps), (main row, mirror row) pairs per entry, by LDS float atomics; the
-// tile is then added to the projection with one global atomic per non-zero
-// entry. Direct variant: global atomics per tap.
+// taps), one plane for main rows and one for mirror rows, as fixed-point
+// integer atomics; the tiles are then added to the projection with one
+// global atomic per non-zero pixel. Direct variant: global atomics per tap.
 // ------------------------------------------------------------------------
 
 __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_t nv, int32_t a,
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
                                                             const float* __restrict__ vol,
                                                             float* __restrict__ q,
                                                             int64_t vstride, float scale) {
-  extern __shared__ int2 atile[];
+  extern __shared__ int atile[];
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
   __shared__ uint32_t hist[kMaxStageViews * kHistStride];
   __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
@@ -593,7 +593,14 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   const int32_t sr = tid / tuf, sc = tid - sr * tuf;
   for (int32_t s0 = 0; s0 < vb.nviews; s0 += ts.vc) {
     const int32_t nvc = min(ts.vc, vb.nviews - s0);
-    for (int32_t e = tid; e < nvc * slot; e += kThreads) atile[e] = make_int2(0, 0);
+    // Main rows in planes [0, vc) and mirror rows in planes [vc, 2 vc), one
+    // 32-bit word per pixel: all LDS banks serve the adds (interleaved
+    // (main, mirror) pairs reached only half of them and conflicted 10-way).
+    int* const mtile = atile + ts.vc * slot;
+    for (int32_t e = tid; e < nvc * slot; e += kThreads) {
+      atile[e] = 0;
+      if (MIRROR) mtile[e] = 0;
+    }
     for (int32_t e = tid; e < nvc * kHistStride; e += kThreads) hist[e] = 0u;
     if (tid < nvc) kcount[tid] = mbits[tid] = 0u;
     __syncthreads();
@@ -622,7 +629,10 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
         if (!(km > 0.0f)) continue;  // nothing reaches this view (uniform)
         const ColumnF32 c = column_f32(bvs[s0 + sl], bc.txf, bc.tyf, kvf);
         const uint32_t nu = min(c.nu, static_cast<uint32_t>(ts.tu - 1));
-        int* base = reinterpret_cast<int*>(atile + sl * slot + nu * tvp + c.nvb);
+        int* const base = atile + sl * slot + nu * tvp + c.nvb;
+        int* const base1 = base + tvp;  // pixel column u + 1
+        int* const mbase = mtile + sl * slot + nu * tvp + c.nvb;
+        int* const mbase1 = mbase + tvp;
         const float ws = c.w * (2147483648.0f / (1.01f * km));
         const float du0 = 1.0f - c.du;
 #pragma unroll
@@ -630,20 +640,19 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
           uint32_t dn;
           float fr;
           voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
-          int* e = base + 2 * dn;  // int2 entries: (main, mirror)
           const float val = ws * x[t];
           const float wa = val - val * fr, wb = val * fr;
-          atomicAdd(e, __float2int_rn(wa * du0));
-          atomicAdd(e + 2 * tvp, __float2int_rn(wa * c.du));
-          atomicAdd(e + 2, __float2int_rn(wb * du0));
-          atomicAdd(e + 2 * tvp + 2, __float2int_rn(wb * c.du));
+          atomicAdd(base + dn, __float2int_rn(wa * du0));
+          atomicAdd(base1 + dn, __float2int_rn(wa * c.du));
+          atomicAdd(base + dn + 1, __float2int_rn(wb * du0));
+          atomicAdd(base1 + dn + 1, __float2int_rn(wb * c.du));
           if (MIRROR) {
             const float vm = ws * xm[t];
             const float ma = vm - vm * fr, mb = vm * fr;
-            atomicAdd(e + 1, __float2int_rn(ma * du0));
-            atomicAdd(e + 2 * tvp + 1, __float2int_rn(ma * c.du));
-            atomicAdd(e + 3, __float2int_rn(mb * du0));
-            atomicAdd(e + 2 * tvp + 3, __float2int_rn(mb * c.du));
+            atomicAdd(mbase + dn, __float2int_rn(ma * du0));
+            atomicAdd(mbase1 + dn, __float2int_rn(ma * c.du));
+            atomicAdd(mbase + dn + 1, __float2int_rn(mb * du0));
+            atomicAdd(mbase1 + dn + 1, __float2int_rn(mb * c.du));
           }
         }
       }
@@ -660,15 +669,17 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
                             __uint_as_float(mbits[sl]) * (1.0f / 2147483648.0f);
         float* qs = q + s * vstride + gu;
         for (int32_t r = sr; r < tv; r += rstep) {
-          const int2 e = atile[sl * slot + sc * tvp + r];
+          const int32_t at = sl * slot + sc * tvp + r;
+          const int32_t ex = atile[at];
           const int32_t gr = bvs[s].org_v + r;
-          if (e.x != 0 && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv))
-            unsafeAtomicAdd(qs + static_cast<int64_t>(gr) * gc.nu, static_cast<float>(e.x) * inv_s);
+          if (ex != 0 && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv))
+            unsafeAtomicAdd(qs + static_cast<int64_t>(gr) * gc.nu, static_cast<float>(ex) * inv_s);
           if (MIRROR) {
+            const int32_t ey = mtile[at];
             const int32_t gm = gc.mirror_g - gr;
-            if (e.y != 0 && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv))
+            if (ey != 0 && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv))
               unsafeAtomicAdd(qs + static_cast<int64_t>(gm) * gc.nu,
-                              static_cast<float>(e.y) * inv_s);
+                              static_cast<float>(ey) * inv_s);
           }
         }
       }
