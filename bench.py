@@ -188,6 +188,8 @@ def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel
         "kernel": kernel, "launches_per_step": launches,
         "avg_launch_ms": round(per_launch_s * 1e3, 3),
         "valu_roof_gups": round(valu_roof, 1), "lds_roof_gups": round(lds_roof, 1),
+        "hbm_achieved_GBps": None if traffic is None else round(traffic / per_launch_s / 1e9, 1),
+        "hbm_peak_GBps": HBM_PEAK / 1e9,
         "hbm_algorithmic_bytes_per_launch": round(updates_per_launch * (
             8.0 / views_per_launch + g.nu * g.nv * q_bytes / (g.nx * g.ny * nz))),
     }

@@ -1,0 +1,297 @@
+// Adjoint of the back-projection (forward projection) for gfx950: every
+// voxel scatters scale * W * w_tap * vol into its four taps, with exactly the
+// coordinates and weights of the matching back-projection variant (same
+// brick setup, brick.h; FP32 columns for the tiled variant, FP64 columns for
+// the direct one), so each is the transpose of its back-projector up to
+// rounding.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "brick.h"
+
+namespace fdk {
+namespace {
+
+// Tiled variant: per view, the brick's splats accumulate in LDS tiles with
+// the back-projector's transposed layout (one more column, for the u + 1
+// taps), one plane for main rows and one for mirror rows, as fixed-point
+// integer atomics; the tiles are then added to the projection with one
+// global atomic per non-zero pixel. Direct variant: global atomics per tap.
+
+__device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_t nv, int32_t a,
+                                      float du, int32_t ra, int32_t rb, float fr, float val) {
+  const float wa = val * (1.0f - fr), wb = val * fr;
+  const float w[4] = {wa * (1.0f - du), wa * du, wb * (1.0f - du), wb * du};
+  const int32_t cols[4] = {a, a + 1, a, a + 1};
+  const int32_t rows[4] = {ra, ra, rb, rb};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    if (static_cast<uint32_t>(cols[m]) < static_cast<uint32_t>(nu) &&
+        static_cast<uint32_t>(rows[m]) < static_cast<uint32_t>(nv))
+      unsafeAtomicAdd(qs + static_cast<int64_t>(rows[m]) * nu + cols[m], w[m]);
+  }
+}
+
+// Slot order of a lane in the adjoint. Lanes of a wave that share a detector
+// column (along the rays) would otherwise add to the same LDS or global
+// address in the same instruction, which serialises; rotating each lane's
+// walk over its 16 slots by (tx + 4 ty) mod 16 puts such lanes on
+// different rows.
+__device__ __forceinline__ uint32_t slot_rotation() {
+  const uint32_t tx = threadIdx.x % kBrickX, ty = (threadIdx.x / kBrickX) & 3u;
+  return (tx + 4u * ty) & (kBrickZ - 1);
+}
+
+// Voxel values of the thread's column, scaled, in the lane's slot order:
+// x[t] is slot (t + rot) mod 16.
+template <bool MIRROR>
+__device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& run,
+                                            const BrickCoords& bc, const float* __restrict__ vol,
+                                            float scale, uint32_t rot, float* x, float* xm) {
+  const int64_t slice = static_cast<int64_t>(gc.nx) * gc.ny;
+  const int64_t col = static_cast<int64_t>(bc.j) * gc.nx + bc.i;
+#pragma unroll
+  for (int t = 0; t < kBrickZ; ++t) {
+    const int32_t sl = static_cast<int32_t>((t + rot) & (kBrickZ - 1));
+    const bool in = bc.owner && (bc.t0 + sl < run.n);
+    x[t] = in ? scale * vol[static_cast<int64_t>(run.loc_lo + bc.t0 + sl) * slice + col] : 0.0f;
+    xm[t] = (MIRROR && in)
+                ? scale * vol[static_cast<int64_t>(run.loc_hi - bc.t0 - sl) * slice + col]
+                : 0.0f;
+  }
+}
+
+// Fixed-point accumulation for the tiled adjoint. LDS float atomics are
+// slow on gfx950 (about 40x an integer atomic, measured), so splats are
+// accumulated as 32-bit fixed point with integer LDS atomics: exact and
+// independent of order within the workgroup. The scale is chosen per brick
+// and view from a bound on what one pixel can receive:
+//  - a column adds to the pixel columns floor(u) and floor(u) + 1, so pixel
+//    column p hears only from columns with floor(u) in {p - 1, p};
+//  - of a column's 16 slots, those with a tap on row r have v in [r - 1,
+//    r + 1): at most floor(2 / (dv/dk)) + 2 of them (one spare for the
+//    rounding of v), and never more than 16;
+//  - each contribution is at most M = max over columns of max|x| * W.
+// A histogram over floor(u) of the per-column slot bounds gives K, the most
+// contributions any pixel can receive, and S = 2^31 / (1.01 K M) keeps
+// every partial sum, rounding included, inside int32. The quantisation step
+// is then about 2^-31 of K M: the error is far below that of the FP32 sum
+// for the real overlap of a brick's footprint.
+constexpr int32_t kHistStride = kThreads;  // tile columns tu + 1 <= 256
+
+template <bool MIRROR>
+__global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRun run,
+                                                            ViewBatch vb, TileShape ts,
+                                                            const float* __restrict__ vol,
+                                                            float* __restrict__ q,
+                                                            int64_t vstride, float scale) {
+  extern __shared__ int atile[];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  __shared__ uint32_t hist[kMaxStageViews * kHistStride];
+  __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
+  __shared__ uint32_t amax_bits;
+  const int32_t tid = threadIdx.x;
+  const BrickCoords bc = brick_coords(gc, run, ts);
+  if (tid == 0) amax_bits = 0u;
+  if (tid < vb.nviews)
+    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+  const uint32_t rot = slot_rotation();
+  float x[kBrickZ], xm[kBrickZ];
+  load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
+  float amax = 0.0f;
+#pragma unroll
+  for (int t = 0; t < kBrickZ; ++t) amax = fmaxf(amax, fmaxf(fabsf(x[t]), fabsf(xm[t])));
+  __syncthreads();
+  atomicMax(&amax_bits, __float_as_uint(amax));  // non-negative floats order as integers
+  __syncthreads();
+  if (amax_bits == 0u) return;  // an all-zero brick adds nothing (uniform)
+
+  const float kvf = static_cast<float>(gc.kv);
+  const int32_t tuf = ts.tu + 1, tv = ts.tv, tvp = ts.tvp;
+  const int32_t slot = tuf * tvp;
+  const int32_t rstep = kThreads / tuf;
+  const int32_t sr = tid / tuf, sc = tid - sr * tuf;
+  for (int32_t s0 = 0; s0 < vb.nviews; s0 += ts.vc) {
+    const int32_t nvc = min(ts.vc, vb.nviews - s0);
+    // Main rows in planes [0, vc) and mirror rows in planes [vc, 2 vc), one
+    // 32-bit word per pixel: all LDS banks serve the adds (interleaved
+    // (main, mirror) pairs reached only half of them and conflicted 10-way).
+    int* const mtile = atile + ts.vc * slot;
+    for (int32_t e = tid; e < nvc * slot; e += kThreads) {
+      atile[e] = 0;
+      if (MIRROR) mtile[e] = 0;
+    }
+    for (int32_t e = tid; e < nvc * kHistStride; e += kThreads) hist[e] = 0u;
+    if (tid < nvc) kcount[tid] = mbits[tid] = 0u;
+    __syncthreads();
+    // Bounds: histogram of the columns' slot bounds over floor(u), and the
+    // largest contribution.
+    if (bc.owner) {
+      for (int32_t sl = 0; sl < nvc; ++sl) {
+        const ColumnF32 c = column_f32(bvs[s0 + sl], bc.txf, bc.tyf, kvf);
+        const uint32_t nu = min(c.nu, static_cast<uint32_t>(ts.tu - 1));
+        const float ks = fminf(static_cast<float>(kBrickZ), floorf(2.0f / c.dvk) + 2.0f);
+        atomicAdd(&hist[sl * kHistStride + nu], static_cast<uint32_t>(ks));
+        atomicMax(&mbits[sl], __float_as_uint(amax * c.w));
+      }
+    }
+    __syncthreads();
+    if (tid < tuf) {
+      for (int32_t sl = 0; sl < nvc; ++sl) {
+        const uint32_t* h = hist + sl * kHistStride;
+        atomicMax(&kcount[sl], (tid < ts.tu ? h[tid] : 0u) + (tid > 0 ? h[tid - 1] : 0u));
+      }
+    }
+    __syncthreads();
+    if (bc.owner) {
+      for (int32_t sl = 0; sl < nvc; ++sl) {
+        const float km = static_cast<float>(kcount[sl]) * __uint_as_float(mbits[sl]);
+        if (!(km > 0.0f)) continue;  // nothing reaches this view (uniform)
+        const ColumnF32 c = column_f32(bvs[s0 + sl], bc.txf, bc.tyf, kvf);
+        const uint32_t nu = min(c.nu, static_cast<uint32_t>(ts.tu - 1));
+        int* const base = atile + sl * slot + nu * tvp + c.nvb;
+        int* const base1 = base + tvp;  // pixel column u + 1
+        int* const mbase = mtile + sl * slot + nu * tvp + c.nvb;
+        int* const mbase1 = mbase + tvp;
+        const float ws = c.w * (2147483648.0f / (1.01f * km));
+        const float du0 = 1.0f - c.du;
+#pragma unroll
+        for (int t = 0; t < kBrickZ; ++t) {
+          uint32_t dn;
+          float fr;
+          voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
+          const float val = ws * x[t];
+          const float wa = val - val * fr, wb = val * fr;
+          atomicAdd(base + dn, __float2int_rn(wa * du0));
+          atomicAdd(base1 + dn, __float2int_rn(wa * c.du));
+          atomicAdd(base + dn + 1, __float2int_rn(wb * du0));
+          atomicAdd(base1 + dn + 1, __float2int_rn(wb * c.du));
+          if (MIRROR) {
+            const float vm = ws * xm[t];
+            const float ma = vm - vm * fr, mb = vm * fr;
+            atomicAdd(mbase + dn, __float2int_rn(ma * du0));
+            atomicAdd(mbase1 + dn, __float2int_rn(ma * c.du));
+            atomicAdd(mbase + dn + 1, __float2int_rn(mb * du0));
+            atomicAdd(mbase1 + dn + 1, __float2int_rn(mb * c.du));
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // Flush: entry (r, c) holds pixel (org_u + c, org_v + r) and, for
+    // mirrored runs, pixel (org_u + c, G - org_v - r).
+    if (sr < rstep) {
+      for (int32_t sl = 0; sl < nvc; ++sl) {
+        const int32_t s = s0 + sl;
+        const int32_t gu = bvs[s].org_u + sc;
+        if (static_cast<uint32_t>(gu) >= static_cast<uint32_t>(gc.nu)) continue;
+        const float inv_s = 1.01f * static_cast<float>(kcount[sl]) *
+                            __uint_as_float(mbits[sl]) * (1.0f / 2147483648.0f);
+        float* qs = q + s * vstride + gu;
+        for (int32_t r = sr; r < tv; r += rstep) {
+          const int32_t at = sl * slot + sc * tvp + r;
+          const int32_t ex = atile[at];
+          const int32_t gr = bvs[s].org_v + r;
+          if (ex != 0 && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv))
+            unsafeAtomicAdd(qs + static_cast<int64_t>(gr) * gc.nu, static_cast<float>(ex) * inv_s);
+          if (MIRROR) {
+            const int32_t ey = mtile[at];
+            const int32_t gm = gc.mirror_g - gr;
+            if (ey != 0 && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv))
+              unsafeAtomicAdd(qs + static_cast<int64_t>(gm) * gc.nu,
+                              static_cast<float>(ey) * inv_s);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool MIRROR>
+__global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceRun run,
+                                                             ViewBatch vb, TileShape ts,
+                                                             const float* __restrict__ vol,
+                                                             float* __restrict__ q,
+                                                             int64_t vstride, float scale) {
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  const int32_t tid = threadIdx.x;
+  const BrickCoords bc = brick_coords(gc, run, ts);
+  if (tid < vb.nviews)
+    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+  const uint32_t rot = slot_rotation();
+  float x[kBrickZ], xm[kBrickZ];
+  load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
+  __syncthreads();
+  if (!bc.owner) return;
+  for (int32_t s = 0; s < vb.nviews; ++s) {
+    const ColumnF32 c = column_f64(gc, vb.view[s], bvs[s], bc.i, bc.j, bc.kb);
+    float* qs = q + s * vstride;
+    const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
+    const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);
+#pragma unroll
+    for (int t = 0; t < kBrickZ; ++t) {
+      const int32_t sl = static_cast<int32_t>((t + rot) & (kBrickZ - 1));
+      if (bc.t0 + sl >= run.n) continue;
+      uint32_t dn;
+      float fr;
+      voxel_row_off(c.fvb, c.dvk, sl, &dn, &fr);
+      const int32_t n = nb + static_cast<int32_t>(dn);
+      splat(qs, gc.nu, gc.nv, a, c.du, n, n + 1, fr, c.w * x[t]);
+      if (MIRROR) {
+        const int32_t m = gc.mirror_g - n;
+        splat(qs, gc.nu, gc.nv, a, c.du, m, m - 1, fr, c.w * xm[t]);
+      }
+    }
+  }
+}
+
+__global__ void fill_zero_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; m < n; m += stride)
+    p[m] = 0.0f;
+}
+
+}  // namespace
+
+int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
+                           const TileShape& ts, const float* vol, float* q, int64_t vstride,
+                           float scale, void* stream) {
+  const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
+  const dim3 grid(static_cast<uint32_t>(nwg)), block(kThreads);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ts.vc > 0) {
+    // Adjoint tile: one more column than the back-projection tile, float2
+    // entries; it always fits where the back-projection tile does.
+    TileShape tf = ts;
+    const int64_t per_view = static_cast<int64_t>(ts.tu + 1) * ts.tvp * sizeof(int2);
+    tf.vc = static_cast<int32_t>(std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view));
+    const size_t lds = static_cast<size_t>(tf.vc) * per_view;
+    if (run.mirror)
+      hipLaunchKernelGGL((fp_tiled_kernel<true>), grid, block, lds, st, gc, run, vb, tf, vol,
+                         q, vstride, scale);
+    else
+      hipLaunchKernelGGL((fp_tiled_kernel<false>), grid, block, lds, st, gc, run, vb, tf, vol,
+                         q, vstride, scale);
+  } else {
+    if (run.mirror)
+      hipLaunchKernelGGL((fp_direct_kernel<true>), grid, block, 0, st, gc, run, vb, ts, vol, q,
+                         vstride, scale);
+    else
+      hipLaunchKernelGGL((fp_direct_kernel<false>), grid, block, 0, st, gc, run, vb, ts, vol, q,
+                         vstride, scale);
+  }
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_fill_zero(float* p, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), p, n);
+  return static_cast<int>(hipGetLastError());
+}
+
+}  // namespace fdk
