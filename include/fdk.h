@@ -117,6 +117,19 @@ FDK_API fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t
                            int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
                            void* stream);
 
+/* Adjoint (transpose) of fdk_filter for FP32 gradients: for all E and G,
+ *     <fdk_filter(E), G> = <E, fdk_filter_adjoint(G)>.
+ * The ramp kernel is even, so the row convolution is its own transpose; the
+ * cosine weight, applied before the convolution in fdk_filter, multiplies
+ * the convolution's output here:
+ *     E_grad(u) = F_cos(u, v) * tau * sum_n h(u - n) * G(n).
+ * q_grad, e_grad: device FP32 (nviews, Nv, Nu), not overlapping. Used to
+ * differentiate a reconstruction with respect to the line integrals.
+ * Errors: as fdk_filter. */
+FDK_API fdk_status fdk_filter_adjoint(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                                      const float* q_grad, float* e_grad, fdk_filter_kind kind,
+                                      void* stream);
+
 /* Back-projection, Alg. 2 computed as Alg. 4. For every voxel (i, j, k)
  * the slab holds, with [x, y, z] = P_s [i, j, k, 1], f = 1/z, W = f^2,
  * (u, v) = (x f, y f):

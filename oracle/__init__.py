@@ -16,6 +16,7 @@ Each wrapped routine names the passage of Chen et al. (SC'19) it follows:
   forward_project     the exact transpose of backproject
   filter              Alg. 1: cosine weight, then ramp convolution per row
   filter_rows         Alg. 1 on a list of detector rows
+  filter_adjoint      the transpose of Alg. 1
   phantom_project     analytic line integrals of an ellipsoid phantom
 """
 from __future__ import annotations
@@ -84,6 +85,8 @@ def lib():
         L.or_cos_weight.argtypes = [_DP, C.c_double, C.c_double]
         L.or_filter.restype = C.c_int
         L.or_filter.argtypes = [_DP, C.c_int64, C.c_int, _DP, _DP]
+        L.or_filter_adjoint.restype = C.c_int
+        L.or_filter_adjoint.argtypes = [_DP, C.c_int64, C.c_int, _DP, _DP]
         L.or_filter_rows.restype = C.c_int
         L.or_filter_rows.argtypes = [_DP, C.c_int64, _IP, C.c_int, _DP, _DP]
         L.or_hash_fill.argtypes = [C.c_uint64, C.c_int64, _UP, C.c_int, _DP]
@@ -251,6 +254,16 @@ def filter(geom, e, kind="ramlak") -> np.ndarray:
     out = np.zeros_like(e)
     if lib().or_filter(_d(gvec(geom)), e.shape[0], FILTERS[kind], _d(e), _d(out)):
         raise MemoryError("oracle filter")
+    return out
+
+
+def filter_adjoint(geom, gq, kind="ramlak") -> np.ndarray:
+    """Transpose of the filtering stage (Alg. 1), FP64, (nviews, Nv, Nu)."""
+    gq = _f64(gq)
+    assert gq.shape[1:] == (geom.nv, geom.nu)
+    out = np.zeros_like(gq)
+    if lib().or_filter_adjoint(_d(gvec(geom)), gq.shape[0], FILTERS[kind], _d(gq), _d(out)):
+        raise MemoryError("oracle filter adjoint")
     return out
 
 

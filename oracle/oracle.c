@@ -490,6 +490,32 @@ int or_filter_rows(const double* g, int64_t nrows, const int64_t* rows_v, int ki
   return failed ? -1 : 0;
 }
 
+/* Transpose of Alg. 1 on whole views: for the operator
+ * Q(b, a) = tau * sum_n h(a - n) * F_cos(n, b) * E(b, n), the transpose maps G
+ * to E_grad(b, n) = F_cos(n, b) * tau * sum_a h(a - n) * G(b, a), the sum over
+ * the forward operator's output index written out as such. g and out are
+ * (nviews, nv, nu). Returns -1 on allocation failure. */
+int or_filter_adjoint(const double* g, int64_t nviews, int kind, const double* gq, double* out) {
+  const int64_t nu = G_NU(g), nv = G_NV(g);
+  const double tau = g[8] * g[12] / g[13];
+  double* h = (double*)malloc((size_t)(2 * nu + 1) * sizeof(double));
+  if (!h) return -1;
+  for (int64_t n = -nu; n <= nu; ++n) h[n + nu] = or_ramp_kernel(kind, n, tau);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int64_t s = 0; s < nviews; ++s)
+    for (int64_t b = 0; b < nv; ++b) {
+      const double* grow = gq + (s * nv + b) * nu;
+      double* erow = out + (s * nv + b) * nu;
+      for (int64_t n = 0; n < nu; ++n) {
+        double acc = 0.0;
+        for (int64_t a = 0; a < nu; ++a) acc += h[a - n + nu] * grow[a];
+        erow[n] = or_cos_weight(g, (double)n, (double)b) * tau * acc;
+      }
+    }
+  free(h);
+  return 0;
+}
+
 /* Alg. 1 on whole views: e and out are (nviews, nv, nu). */
 int or_filter(const double* g, int64_t nviews, int kind, const double* e, double* out) {
   const int64_t nv = G_NV(g);

@@ -20,7 +20,8 @@ import torch
 
 __all__ = [
     "Geometry", "FDKError", "lib", "backproject", "forward_project", "filter",
-    "fdk_scale", "FDKBackprojection", "fdk_backprojection",
+    "filter_adjoint", "slab_rows", "fdk_scale", "FDKBackprojection", "fdk_backprojection",
+    "FDKReconstruction", "fdk_reconstruction",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -101,6 +102,9 @@ def lib():
         L.fdk_filter_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int,
                                       C.c_void_p]
+        L.fdk_filter_adjoint.restype = C.c_int
+        L.fdk_filter_adjoint.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int,
+                                         C.c_void_p]
         L.fdk_slab_rows.restype = C.c_int
         L.fdk_slab_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int, C.POINTER(C.c_int32)]
         L.fdk_fdk_scale.restype = C.c_double
@@ -231,6 +235,24 @@ def slab_rows(geom, angles, *, z0: int = 0, nz_local: int | None = None,
     return [(band[2 * n], band[2 * n + 1]) for n in range(2) if band[2 * n + 1] > 0]
 
 
+def filter_adjoint(gq: torch.Tensor, geom, angles, *, view0: int = 0, kind: str = "ramlak",
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """Transpose of the filtering stage for float32 (nviews, Nv, Nu)
+    gradients: the row convolution, then the cosine weight."""
+    _dev(gq, "gq")
+    if gq.dtype != torch.float32 or gq.dim() != 3 or tuple(gq.shape[1:]) != (geom.nv, geom.nu):
+        raise ValueError(f"gq must be float32 (nviews, {geom.nv}, {geom.nu})")
+    if out is None:
+        out = torch.empty_like(gq)
+    _dev(out, "out")
+    if out.dtype != torch.float32 or out.shape != gq.shape:
+        raise ValueError("out must be float32 with gq's shape")
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_filter_adjoint(C.byref(cg), view0, gq.shape[0], C.c_void_p(gq.data_ptr()),
+                                    C.c_void_p(out.data_ptr()), _FILTERS[kind], _stream(gq)))
+    return out
+
+
 def fdk_scale(geom, angles) -> float:
     """pi d^2 / Np, the FDK constant for a full circular scan."""
     cg, _keep = _cgeom(geom, angles)
@@ -267,3 +289,41 @@ class FDKBackprojection(torch.autograd.Function):
 
 def fdk_backprojection(q, geom, angles, scale=1.0):
     return FDKBackprojection.apply(q, geom, angles, scale)
+
+
+class FDKReconstruction(torch.autograd.Function):
+    """Differentiable FDK from line integrals: forward filters E (cosine
+    weight and ramp, Alg. 1, FP32) and back-projects; backward applies the
+    matched forward projector and then the filter's transpose, so gradients
+    reach the raw line integrals. e: (B, nviews, Nv, Nu) or (nviews, Nv, Nu)
+    float32."""
+
+    @staticmethod
+    def forward(ctx, e, geom, angles, kind="ramlak", scale=1.0):
+        ctx.geom, ctx.angles = geom, np.asarray(angles, np.float64)
+        ctx.kind, ctx.scale = kind, float(scale)
+        batched = e.dim() == 4
+        es = e if batched else e.unsqueeze(0)
+        vols = [backproject(filter(es[b].contiguous(), geom, ctx.angles, kind=kind), geom,
+                            ctx.angles, scale=ctx.scale) for b in range(es.shape[0])]
+        out = torch.stack(vols)
+        return out if batched else out[0]
+
+    @staticmethod
+    def backward(ctx, gvol):
+        batched = gvol.dim() == 4
+        gv = gvol if batched else gvol.unsqueeze(0)
+        ge = torch.stack([
+            filter_adjoint(forward_project(gv[b].to(torch.float32).contiguous(), ctx.geom,
+                                           ctx.angles, scale=ctx.scale),
+                           ctx.geom, ctx.angles, kind=ctx.kind)
+            for b in range(gv.shape[0])])
+        return (ge if batched else ge[0]), None, None, None, None
+
+
+def fdk_reconstruction(e, geom, angles, kind="ramlak", scale=None):
+    """FDK of line integrals e, differentiable with respect to e. scale
+    defaults to the FDK constant pi d^2 / Np."""
+    if scale is None:
+        scale = fdk_scale(geom, angles)
+    return FDKReconstruction.apply(e, geom, angles, kind, scale)

@@ -268,10 +268,12 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
   return ok();
 }
 
-fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
-                           int32_t nrows, const float* e, int64_t e_view_stride, void* q,
-                           int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
-                           void* stream) {
+namespace {
+// Filtering of a row band, or its adjoint (FP32 output only).
+fdk_status filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
+                       int32_t nrows, const float* e, int64_t e_view_stride, void* q,
+                       int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
+                       bool adjoint, void* stream) {
   fdk_status st = check_geometry(g);
   if (st) return st;
   if ((st = check_views(g, view0, nviews))) return st;
@@ -297,10 +299,30 @@ fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews,
     return fail(FDK_ERR_INVALID_ARG, "filter input and output overlap");
   const fdk::GeoConst gc = make_geo(g);
   const fdk::RowBand rb{nviews, v0, nrows, e_view_stride, q_view_stride};
-  if (int err = fdk::launch_filter(gc, g->du, g->dv, g->sod, g->sdd, rb, e, q, out_dtype, kind,
-                                   stream))
-    return fail(FDK_ERR_HIP, "filter launch failed: HIP error %d", err);
+  const int err = adjoint ? fdk::launch_filter_adjoint(gc, g->du, g->dv, g->sod, g->sdd, rb, e,
+                                                       static_cast<float*>(q), kind, stream)
+                          : fdk::launch_filter(gc, g->du, g->dv, g->sod, g->sdd, rb, e, q,
+                                               out_dtype, kind, stream);
+  if (err) return fail(FDK_ERR_HIP, "filter launch failed: HIP error %d", err);
   return ok();
+}
+}  // namespace
+
+fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
+                           int32_t nrows, const float* e, int64_t e_view_stride, void* q,
+                           int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
+                           void* stream) {
+  return filter_rows(g, view0, nviews, v0, nrows, e, e_view_stride, q, q_view_stride, out_dtype,
+                     kind, false, stream);
+}
+
+fdk_status fdk_filter_adjoint(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                              const float* q_grad, float* e_grad, fdk_filter_kind kind,
+                              void* stream) {
+  if (!g) return fail(FDK_ERR_INVALID_ARG, "geometry pointer is NULL");
+  const int64_t full = (int64_t)g->nu * g->nv;
+  return filter_rows(g, view0, nviews, 0, g->nv, q_grad, full, e_grad, full, FDK_F32, kind, true,
+                     stream);
 }
 
 fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local, fdk_slab_kind slab,
@@ -369,6 +391,7 @@ fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local, fd
   }
   return ok();
 }
+
 
 fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews, const float* e,
                       void* q, fdk_dtype out_dtype, fdk_filter_kind kind, void* stream) {

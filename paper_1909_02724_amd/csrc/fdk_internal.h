@@ -94,5 +94,9 @@ struct RowBand {
 int launch_filter(const GeoConst& gc, double du, double dv, double sod, double sdd,
                   const RowBand& rb, const float* e, void* q, fdk_dtype out_dtype,
                   fdk_filter_kind kind, void* stream);
+// Adjoint of launch_filter (FP32): convolution first, cosine weight after.
+int launch_filter_adjoint(const GeoConst& gc, double du, double dv, double sod, double sdd,
+                          const RowBand& rb, const float* q_grad, float* e_grad,
+                          fdk_filter_kind kind, void* stream);
 
 }  // namespace fdk

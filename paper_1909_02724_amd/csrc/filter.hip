@@ -1,5 +1,8 @@
 // Filtering stage (Alg. 1) on gfx950: cosine weighting, then linear
-// convolution of every detector row with the sampled ramp kernel.
+// convolution of every detector row with the sampled ramp kernel. The
+// adjoint (ADJ) runs the same convolution first and weights its output: the
+// kernel is even, so the convolution matrix is symmetric, and the weighting
+// is diagonal.
 //
 // Short rows (and rows too long for the FFT tile) use a direct convolution:
 // one workgroup per row, the weighted row and the kernel taps in LDS.
@@ -71,7 +74,7 @@ __device__ __forceinline__ BandRow band_row(const RowBand& rb, int32_t nu, int64
                  static_cast<int32_t>(rb.v0 + r)};
 }
 
-template <typename OutT>
+template <typename OutT, bool ADJ>
 __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
     GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
     const float* __restrict__ e, OutT* __restrict__ q) {
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
   const int32_t b = br.b;
   const float* er = e + br.ein;
   for (int32_t a = threadIdx.x; a < nu; a += kFilterThreads) {
-    et[a] = er[a] * cos_weight(gc, du, dv, sdd, a, b);
+    et[a] = ADJ ? er[a] : er[a] * cos_weight(gc, du, dv, sdd, a, b);
     h[a] = static_cast<float>(tau * ramp_tap(kind, a, tau));
   }
   __syncthreads();
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
       const int32_t d = a - n;
       acc = fmaf(h[d < 0 ? -d : d], et[n], acc);
     }
-    store_q(qr + a, acc);
+    store_q(qr + a, ADJ ? acc * cos_weight(gc, du, dv, sdd, a, b) : acc);
   }
 }
 
@@ -123,7 +126,7 @@ __device__ __forceinline__ int32_t bitrev(int32_t n, int32_t logl) {
   return static_cast<int32_t>(__builtin_bitreverse32(static_cast<uint32_t>(n)) >> (32 - logl));
 }
 
-template <typename OutT>
+template <typename OutT, bool ADJ>
 __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(
     GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
     int32_t logl, int64_t nrows, const float* __restrict__ e, OutT* __restrict__ q) {
@@ -162,8 +165,9 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(
     for (int32_t n = threadIdx.x; n < L; n += kFilterThreads) {
       float re = 0.0f, im = 0.0f;
       if (n < nu) {
-        re = e[rowa.ein + n] * cos_weight(gc, du, dv, sdd, n, rowa.b);
-        if (has_b) im = e[rowb.ein + n] * cos_weight(gc, du, dv, sdd, n, rowb.b);
+        re = ADJ ? e[rowa.ein + n] : e[rowa.ein + n] * cos_weight(gc, du, dv, sdd, n, rowa.b);
+        if (has_b)
+          im = ADJ ? e[rowb.ein + n] : e[rowb.ein + n] * cos_weight(gc, du, dv, sdd, n, rowb.b);
       }
       x[bitrev(n, logl)] = make_float2(re, im);
     }
@@ -190,14 +194,19 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(
     fft_inplace(x, tw, logl);
     for (int32_t n = threadIdx.x; n < nu; n += kFilterThreads) {
       const float2 v = x[n];
-      store_q(q + rowa.qout + n, v.x);
-      if (has_b) store_q(q + rowb.qout + n, -v.y);
+      if (ADJ) {
+        store_q(q + rowa.qout + n, v.x * cos_weight(gc, du, dv, sdd, n, rowa.b));
+        if (has_b) store_q(q + rowb.qout + n, -v.y * cos_weight(gc, du, dv, sdd, n, rowb.b));
+      } else {
+        store_q(q + rowa.qout + n, v.x);
+        if (has_b) store_q(q + rowb.qout + n, -v.y);
+      }
     }
     __syncthreads();
   }
 }
 
-template <typename OutT>
+template <typename OutT, bool ADJ>
 int launch_filter_t(const GeoConst& gc, const RowBand& rb, double du, double dv, double sdd,
                     double tau, int kind, const float* e, void* q, hipStream_t st) {
   OutT* qt = static_cast<OutT*>(q);
@@ -209,16 +218,16 @@ int launch_filter_t(const GeoConst& gc, const RowBand& rb, double du, double dv,
     const size_t lds = (static_cast<size_t>(L) + L / 2) * sizeof(float2);
     const uint32_t groups = static_cast<uint32_t>((nrows + 2 * kFftRowPairs - 1) / (2 * kFftRowPairs));
     if (lds > 65536) {
-      hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&filter_fft_kernel<OutT>),
+      hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&filter_fft_kernel<OutT, ADJ>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(lds));
       if (err != hipSuccess) return static_cast<int>(err);
     }
-    hipLaunchKernelGGL(filter_fft_kernel<OutT>, dim3(groups), dim3(kFilterThreads), lds, st, gc,
+    hipLaunchKernelGGL((filter_fft_kernel<OutT, ADJ>), dim3(groups), dim3(kFilterThreads), lds, st, gc,
                        rb, du, dv, sdd, tau, kind, logl, nrows, e, qt);
   } else {
     const size_t lds = 2 * static_cast<size_t>(gc.nu) * sizeof(float);
-    hipLaunchKernelGGL(filter_direct_kernel<OutT>, dim3(static_cast<uint32_t>(nrows)),
+    hipLaunchKernelGGL((filter_direct_kernel<OutT, ADJ>), dim3(static_cast<uint32_t>(nrows)),
                        dim3(kFilterThreads), lds, st, gc, rb, du, dv, sdd, tau, kind, e, qt);
   }
   return static_cast<int>(hipGetLastError());
@@ -233,13 +242,21 @@ int launch_filter(const GeoConst& gc, double du, double dv, double sod, double s
   const double tau = du * sod / sdd;  // pixel pitch scaled to the rotation axis
   switch (out_dtype) {
     case FDK_F32:
-      return launch_filter_t<float>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
+      return launch_filter_t<float, false>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
     case FDK_F16:
-      return launch_filter_t<f16_t>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
+      return launch_filter_t<f16_t, false>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
     case FDK_BF16:
-      return launch_filter_t<bf16_t>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
+      return launch_filter_t<bf16_t, false>(gc, rb, du, dv, sdd, tau, kind, e, q, st);
   }
   return static_cast<int>(hipErrorInvalidValue);
+}
+
+int launch_filter_adjoint(const GeoConst& gc, double du, double dv, double sod, double sdd,
+                          const RowBand& rb, const float* q_grad, float* e_grad,
+                          fdk_filter_kind kind, void* stream) {
+  const double tau = du * sod / sdd;
+  return launch_filter_t<float, true>(gc, rb, du, dv, sdd, tau, kind, q_grad, e_grad,
+                                      static_cast<hipStream_t>(stream));
 }
 
 }  // namespace fdk

@@ -26,7 +26,8 @@ def declared_functions():
 def test_header_symbols_exported():
     L = fdk.lib()
     names = declared_functions()
-    assert {"fdk_filter", "fdk_backproject", "fdk_forward_project", "fdk_fdk_scale",
+    assert {"fdk_filter", "fdk_filter_rows", "fdk_filter_adjoint", "fdk_backproject",
+            "fdk_forward_project", "fdk_slab_rows", "fdk_fdk_scale",
             "fdk_last_error"} <= set(names)
     for n in names:
         assert hasattr(L, n), n
@@ -189,3 +190,16 @@ def test_slab_rows_validation():
     assert L.fdk_slab_rows(C.byref(cg), 0, 5, 1, band) == 1
     assert L.fdk_slab_rows(C.byref(cg), 0, 8, 0, band) == 0
     assert band[1] > 0
+
+
+def test_filter_adjoint_validation():
+    L = fdk.lib()
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    assert L.fdk_filter_adjoint(C.byref(cg), 0, 4, FAKE, FAKE, 9, None) == 2
+    assert "filter kind" in L.fdk_last_error().decode()
+    assert L.fdk_filter_adjoint(C.byref(cg), 10, 4, FAKE, C.c_void_p(0x10000000), 0, None) == 1
+    assert "view range" in L.fdk_last_error().decode()
+    assert L.fdk_filter_adjoint(C.byref(cg), 0, 4, C.c_void_p(0x1000), C.c_void_p(0x1004), 0,
+                                None) == 1
+    assert "overlap" in L.fdk_last_error().decode()
+    assert L.fdk_filter_adjoint(None, 0, 4, FAKE, FAKE, 0, None) == 1

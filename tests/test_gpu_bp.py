@@ -344,3 +344,54 @@ def test_filter_rows_band_into_full_array(nu):
     assert np.abs(got[:, :v0]).max() == 0 and np.abs(got[:, v0 + nr:]).max() == 0
     ref = oracle.filter(g, e.astype(np.float64), "shepp-logan")
     assert rel_l2(got[:, v0:v0 + nr], ref[:, v0:v0 + nr]) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["ramlak", "shepp-logan"])
+@pytest.mark.parametrize("nu", [200, 700])  # direct and FFT paths
+def test_filter_adjoint_matches_oracle(kind, nu):
+    g = BASE.replace(nu=nu, nv=9, off_u=0.35, off_v=-0.2, du=1.1)
+    ang = synth.angles(3)
+    rng = np.random.default_rng(41)
+    gq = rng.standard_normal((3, g.nv, g.nu)).astype(np.float32)
+    got = host(fdk.filter_adjoint(gpu(gq), g, ang, kind=kind))
+    ref = oracle.filter_adjoint(g, gq.astype(np.float64), kind)
+    err = rel_l2(got, ref)
+    announce(f"  filter adjoint nu={nu} {kind}: rel-L2 {err:.3e}")
+    assert err <= 1e-5
+    e = rng.uniform(0, 5, (3, g.nv, g.nu)).astype(np.float32)
+    fe = host(fdk.filter(gpu(e), g, ang, kind=kind))
+    lhs = float(np.vdot(fe, gq.astype(np.float64)))
+    rhs = float(np.vdot(e.astype(np.float64), got))
+    cs = np.linalg.norm(fe) * np.linalg.norm(gq) + np.linalg.norm(e) * np.linalg.norm(got)
+    assert abs(lhs - rhs) <= 1e-6 * cs
+
+
+def test_fdk_reconstruction_autograd():
+    """Gradient of the whole FDK (filter, then back-projection) with respect
+    to the line integrals: the oracle's forward projection followed by its
+    filter transpose, and finite differences (the map is linear)."""
+    g = BASE.replace(nz=16)
+    ang = synth.angles(24)
+    rng = np.random.default_rng(43)
+    e = gpu(rng.uniform(0, 20, (2, 24, g.nv, g.nu)).astype(np.float32)).requires_grad_(True)
+    w = gpu(rng.standard_normal((2, g.nz, g.ny, g.nx)).astype(np.float32))
+    scale = oracle.fdk_scale(g, 24)
+    vol = fdk.fdk_reconstruction(e, g, ang, kind="shepp-logan")
+    (vol * w).sum().backward()
+    ref_vol = oracle.backproject(g, ang, oracle.filter(g, host(e[0]), "shepp-logan"), scale=scale)
+    assert rel_l2(host(vol[0]), ref_vol) <= 1e-5
+    for b in range(2):
+        ref = oracle.filter_adjoint(g, oracle.forward_project(g, ang, host(w[b]), scale=scale),
+                                    "shepp-logan")
+        err = rel_l2(host(e.grad[b]), ref)
+        announce(f"  FDK gradient [{b}] vs oracle: rel-L2 {err:.3e}")
+        assert err <= 1e-5
+    d = gpu(rng.standard_normal((2, 24, g.nv, g.nu)).astype(np.float32))
+    with torch.no_grad():
+        bd = (fdk.fdk_reconstruction(e + d, g, ang, kind="shepp-logan").double()
+              - fdk.fdk_reconstruction(e - d, g, ang, kind="shepp-logan").double()) / 2.0
+    fd = float((bd * w.double()).sum())
+    an = float((e.grad.double() * d.double()).sum())
+    cs = float(bd.norm() * w.double().norm()) + float(d.double().norm() * e.grad.double().norm())
+    announce(f"  FDK finite difference {fd:.9e} vs analytic {an:.9e}")
+    assert abs(fd - an) <= 1e-6 * cs

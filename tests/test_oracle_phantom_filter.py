@@ -193,3 +193,36 @@ def test_rounding_matches_numpy_f16_and_torch_bf16(orc):
     bf = np.array([orc.round_bf16(float(t)) for t in xf])
     ref = torch.from_numpy(xf).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(bf, ref)
+
+
+@pytest.mark.parametrize("kind", ["ramlak", "shepp-logan"])
+def test_filter_adjoint_is_transpose(orc, kind):
+    """The oracle's adjoint filter is the transpose of its filter: matrix
+    columns built by filtering unit images equal the adjoint's rows (brute
+    force on a small detector), and the dot-product identity holds on random
+    data. A non-square, offset detector keeps the cosine weight asymmetric
+    in u and v, so a weight applied on the wrong side fails."""
+    g = synth.Geom(nx=8, ny=8, nz=8, nu=9, nv=4, sod=30.0, sdd=55.0, du=3.0, dv=2.5,
+                   off_u=0.6, off_v=-0.3)
+    n = g.nv * g.nu
+    A = np.empty((n, n))
+    for m in range(n):
+        e = np.zeros((1, g.nv, g.nu))
+        e.reshape(-1)[m] = 1.0
+        A[:, m] = orc.filter(g, e, kind).reshape(-1)
+    At = np.empty((n, n))
+    for m in range(n):
+        gq = np.zeros((1, g.nv, g.nu))
+        gq.reshape(-1)[m] = 1.0
+        At[:, m] = orc.filter_adjoint(g, gq, kind).reshape(-1)
+    assert np.abs(At - A.T).max() <= 1e-13 * np.abs(A).max()
+    # rows never mix: the operator is block diagonal over detector rows
+    assert np.all(A.reshape(g.nv, g.nu, g.nv, g.nu)[0, :, 1, :] == 0.0)
+    # the weight makes it non-symmetric, so the transpose test has teeth
+    assert np.abs(A - A.T).max() > 1e-3 * np.abs(A).max()
+    rng = np.random.default_rng(9)
+    e = rng.standard_normal((3, g.nv, g.nu))
+    gq = rng.standard_normal((3, g.nv, g.nu))
+    lhs = np.vdot(orc.filter(g, e, kind), gq)
+    rhs = np.vdot(e, orc.filter_adjoint(g, gq, kind))
+    assert abs(lhs - rhs) <= 1e-12 * (np.linalg.norm(e) * np.linalg.norm(gq))
