@@ -27,7 +27,9 @@ into HBM first (untimed); then a producer stream filters them chunk by chunk
 into FP16 buffers while the previous 32 views (two chunks) back-project. A step is one pass over all 4096 views; GUPS counts
 the back-projection launches' event time (the rate the paper reports) and,
 beside it, the whole pipeline's wall time. The default run adds one such
-pass to its line (--no-slab skips it).
+pass to its line (--no-slab skips it), and the time of a SIRT iteration
+(forward projection, weighted residual, back-projection, update) at 256^3
+from 360 views of 384^2 (--no-sirt skips it).
 """
 from __future__ import annotations
 
@@ -94,6 +96,8 @@ def parse():
     ap.add_argument("--no-16bit", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sirt", action="store_true",
+                    help="skip the SIRT leg (256^3, 360 views) of the default run")
     ap.add_argument("--no-slab", action="store_true",
                     help="skip the streamed 4096^2-slab leg of the default run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -170,6 +174,44 @@ def run_slab(steps, warmup, dev):
     del vol, store
     torch.cuda.empty_cache()
     return sum(bp) / len(bp), sum(wall) / len(wall), n_launch, g, cfg
+
+
+def run_sirt(dev, iters=10):
+    """SIRT on the 256^3 / 360-view geometry: weights once, then `iters`
+    iterations (one forward projection and one back-projection each),
+    event-timed on the launch stream."""
+    import torch
+
+    import paper_1909_02724_amd as fdk
+    import synth
+    import synth.gpu as sg
+
+    cfg = synth.config("diff256")
+    g = cfg["geom"]
+    ang = synth.angles(cfg["np"])
+    ell = synth.ellipsoids(cfg["seed"], 16, g)
+    p = sg.phantom_project(g, ang, ell, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    row_inv, col_inv = fdk.sirt_weights(g, ang, device=dev)
+    e1.record(stream)
+    x = torch.zeros_like(col_inv)
+    pt, vt = torch.empty_like(p), torch.empty_like(x)
+    fdk.sirt_iteration(x, p, row_inv, col_inv, g, ang, proj_tmp=pt, vol_tmp=vt)  # warm
+    torch.cuda.synchronize()
+    e1b = torch.cuda.Event(enable_timing=True)
+    e1b.record(stream)
+    for _ in range(iters):
+        fdk.sirt_iteration(x, p, row_inv, col_inv, g, ang, proj_tmp=pt, vol_tmp=vt)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    it_ms = e1b.elapsed_time(e2) / iters
+    ups = 2.0 * g.nx * g.ny * g.nz * cfg["np"]
+    log(f"sirt256: weights {e0.elapsed_time(e1):.1f} ms, {it_ms:.2f} ms per iteration "
+        f"({gups(ups, it_ms / 1e3):.1f} GUPS over both passes)")
+    return {"sirt256_iter_ms": round(it_ms, 3), "sirt256_gups": round(gups(ups, it_ms / 1e3), 1),
+            "sirt256_weights_ms": round(e0.elapsed_time(e1), 2)}
 
 
 def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic):
@@ -329,6 +371,9 @@ def main():
     # ---- roofline of the dominant kernel (the back-projection launches) ----
     roofline = roofline_of(ms32, launches, updates, g, 32, 4.0, "bp_tiled_mirror_kernel<float>",
                            profiled_traffic(args.workload))
+
+    if not args.no_sirt and args.workload == "bp2048":
+        result_extra.update(run_sirt(dev))
 
     if not args.no_slab and args.workload == "bp2048":
         del q32

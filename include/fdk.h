@@ -71,6 +71,8 @@ typedef enum { FDK_SLAB_CONTIGUOUS = 0, FDK_SLAB_MIRROR_PAIR = 1 } fdk_slab_kind
 
 /* flags: accumulate into the output instead of overwriting it. */
 #define FDK_ACCUMULATE 1u
+/* flags of fdk_sirt_iteration: clamp the updated volume at zero. */
+#define FDK_NONNEG 2u
 
 /* Circular-orbit cone-beam geometry (Table 1; projection matrix Eq. 2).
  * The volume centre (voxel ((Nx-1)/2, (Ny-1)/2, (Nz-1)/2)) is on the
@@ -180,6 +182,37 @@ FDK_API fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int
  * for a null band. */
 FDK_API fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local,
                          fdk_slab_kind slab, int32_t band[4]);
+
+/* Iterative reconstruction with the matched pair (the paper names iterative
+ * methods, which call the back-projection repeatedly, as a use of it): SIRT
+ * (simultaneous iterative reconstruction, Gilbert 1972) with F =
+ * fdk_forward_project and B = fdk_backproject at scale 1 over views
+ * [view0, view0 + nviews) and the slab (z0, nz_local, slab as in
+ * fdk_backproject):
+ *     x <- x + lambda * C * B(R * (p - F x)),
+ * R = 1 / max(F 1, 1e-3 max(F 1)) per detector pixel and
+ * C = 1 / max(B 1, 1e-3 max(B 1)) per voxel (the inverse row and column
+ * sums of F; raising sums below 1e-3 of the largest keeps the weights
+ * continuous where rays or voxels are barely covered).
+ *
+ * fdk_sirt_weights writes R into row_inv (device FP32 (nviews, Nv, Nu)) and
+ * C into col_inv (device FP32 slab); vol_tmp is a slab-sized device
+ * workspace whose contents are overwritten. */
+FDK_API fdk_status fdk_sirt_weights(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                                    int32_t z0, int32_t nz_local, fdk_slab_kind slab,
+                                    float* row_inv, float* col_inv, float* vol_tmp, void* stream);
+
+/* One SIRT iteration on x (device FP32 slab, updated in place) for measured
+ * projections p (device FP32 (nviews, Nv, Nu)) and weights from
+ * fdk_sirt_weights. flags: 0 or FDK_NONNEG. proj_tmp (projection-sized) and
+ * vol_tmp (slab-sized) are device workspaces; neither may alias an input.
+ * Errors: as fdk_backproject, plus FDK_ERR_INVALID_ARG for a null or
+ * aliased buffer, a non-finite lambda or unknown flags. */
+FDK_API fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                                      const float* p, const float* row_inv, const float* col_inv,
+                                      float* x, int32_t z0, int32_t nz_local, fdk_slab_kind slab,
+                                      float lambda, uint32_t flags, float* proj_tmp,
+                                      float* vol_tmp, void* stream);
 
 /* pi * d^2 / Np: the FDK constant (1/2) * (2 pi / Np) * d^2 of a full
  * 360-degree scan, since W = 1/z^2 carries no d^2. Returns NaN for a null

@@ -17,6 +17,7 @@ Each wrapped routine names the passage of Chen et al. (SC'19) it follows:
   filter              Alg. 1: cosine weight, then ramp convolution per row
   filter_rows         Alg. 1 on a list of detector rows
   filter_adjoint      the transpose of Alg. 1
+  sirt                SIRT (Gilbert 1972) with forward_project / backproject
   phantom_project     analytic line integrals of an ellipsoid phantom
 """
 from __future__ import annotations
@@ -309,3 +310,28 @@ def round_f16(x: float) -> float:
 
 def round_bf16(x: float) -> float:
     return lib().or_round_bf16(float(x))
+
+
+SIRT_FLOOR = 1e-3
+
+
+def sirt_weights(geom, angles):
+    """Inverse row and column sums of the forward projector F (the
+    transpose of backproject), each sum raised to at least 1e-3 of the
+    largest: R = 1 / max(F 1, .), C = 1 / max(B 1, .)."""
+    ang = _f64(angles)
+    rs = forward_project(geom, ang, np.ones((geom.nz, geom.ny, geom.nx)))
+    cs = backproject(geom, ang, np.ones((ang.size, geom.nv, geom.nu)))
+    return 1.0 / np.maximum(rs, SIRT_FLOOR * rs.max()), 1.0 / np.maximum(cs, SIRT_FLOOR * cs.max())
+
+
+def sirt(geom, angles, p, n_iter, lam=1.0, nonneg=False, x0=None):
+    """SIRT: x <- x + lam C B(R (p - F x)), FP64, full volume."""
+    R, Cw = sirt_weights(geom, angles)
+    x = np.zeros((geom.nz, geom.ny, geom.nx)) if x0 is None else _f64(x0).copy()
+    for _ in range(n_iter):
+        r = R * (_f64(p) - forward_project(geom, angles, x))
+        x = x + lam * Cw * backproject(geom, angles, r)
+        if nonneg:
+            x = np.maximum(x, 0.0)
+    return x

@@ -21,7 +21,7 @@ import torch
 __all__ = [
     "Geometry", "FDKError", "lib", "backproject", "forward_project", "filter",
     "filter_adjoint", "slab_rows", "fdk_scale", "FDKBackprojection", "fdk_backprojection",
-    "FDKReconstruction", "fdk_reconstruction",
+    "FDKReconstruction", "fdk_reconstruction", "sirt_weights", "sirt_iteration", "sirt",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +29,7 @@ LIB_PATH = os.path.join(_HERE, "libfdk.so")
 
 FDK_OK, FDK_ERR_INVALID_ARG, FDK_ERR_UNSUPPORTED, FDK_ERR_HIP, FDK_ERR_OOM = range(5)
 FDK_ACCUMULATE = 1
+FDK_NONNEG = 2
 _DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
 _FILTERS = {"ramlak": 0, "ram-lak": 0, "shepp-logan": 1, "shepplogan": 1}
 _SLABS = {"contiguous": 0, "mirror_pair": 1}
@@ -104,6 +105,14 @@ def lib():
                                       C.c_void_p]
         L.fdk_filter_adjoint.restype = C.c_int
         L.fdk_filter_adjoint.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int,
+                                         C.c_void_p]
+        L.fdk_sirt_weights.restype = C.c_int
+        L.fdk_sirt_weights.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.fdk_sirt_iteration.restype = C.c_int
+        L.fdk_sirt_iteration.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int,
+                                         C.c_float, C.c_uint32, C.c_void_p, C.c_void_p,
                                          C.c_void_p]
         L.fdk_slab_rows.restype = C.c_int
         L.fdk_slab_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int, C.POINTER(C.c_int32)]
@@ -327,3 +336,59 @@ def fdk_reconstruction(e, geom, angles, kind="ramlak", scale=None):
     if scale is None:
         scale = fdk_scale(geom, angles)
     return FDKReconstruction.apply(e, geom, angles, kind, scale)
+
+
+def _f32_dev(t, shape, name):
+    _dev(t, name)
+    if t.dtype != torch.float32 or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be float32 {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+
+
+def sirt_weights(geom, angles, *, view0: int = 0, nviews: int | None = None, z0: int = 0,
+                 nz_local: int | None = None, slab: str = "contiguous", device="cuda"):
+    """Inverse row sums R (nviews, Nv, Nu) and column sums C (slab) of the
+    forward projector, for SIRT."""
+    nviews = len(angles) - view0 if nviews is None else int(nviews)
+    z0, nzl, sk = _slab(geom, z0, nz_local, slab)
+    row_inv = torch.empty((nviews, geom.nv, geom.nu), dtype=torch.float32, device=device)
+    col_inv = torch.empty((nzl, geom.ny, geom.nx), dtype=torch.float32, device=device)
+    tmp = torch.empty_like(col_inv)
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_sirt_weights(C.byref(cg), view0, nviews, z0, nzl, sk,
+                                  C.c_void_p(row_inv.data_ptr()), C.c_void_p(col_inv.data_ptr()),
+                                  C.c_void_p(tmp.data_ptr()), _stream(tmp)))
+    return row_inv, col_inv
+
+
+def sirt_iteration(x, p, row_inv, col_inv, geom, angles, *, view0: int = 0, z0: int = 0,
+                   slab: str = "contiguous", lam: float = 1.0, nonneg: bool = False,
+                   proj_tmp=None, vol_tmp=None):
+    """One SIRT update of x (slab, in place) towards projections p."""
+    z0, nzl, sk = _slab(geom, z0, x.shape[0], slab)
+    _f32_dev(x, (nzl, geom.ny, geom.nx), "x")
+    _f32_dev(p, (p.shape[0], geom.nv, geom.nu), "p")
+    _f32_dev(row_inv, p.shape, "row_inv")
+    _f32_dev(col_inv, x.shape, "col_inv")
+    proj_tmp = torch.empty_like(p) if proj_tmp is None else proj_tmp
+    vol_tmp = torch.empty_like(x) if vol_tmp is None else vol_tmp
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_sirt_iteration(C.byref(cg), view0, p.shape[0], C.c_void_p(p.data_ptr()),
+                                    C.c_void_p(row_inv.data_ptr()), C.c_void_p(col_inv.data_ptr()),
+                                    C.c_void_p(x.data_ptr()), z0, nzl, sk, float(lam),
+                                    FDK_NONNEG if nonneg else 0, C.c_void_p(proj_tmp.data_ptr()),
+                                    C.c_void_p(vol_tmp.data_ptr()), _stream(x)))
+    return x
+
+
+def sirt(p, geom, angles, n_iter: int, *, lam: float = 1.0, nonneg: bool = False, x0=None,
+         z0: int = 0, nz_local: int | None = None, slab: str = "contiguous"):
+    """n_iter SIRT iterations from x0 (default zero) for projections p
+    (nviews, Nv, Nu) float32 of views [0, nviews)."""
+    row_inv, col_inv = sirt_weights(geom, angles, nviews=p.shape[0], z0=z0, nz_local=nz_local,
+                                    slab=slab, device=p.device)
+    x = torch.zeros_like(col_inv) if x0 is None else x0.clone()
+    proj_tmp, vol_tmp = torch.empty_like(p), torch.empty_like(x)
+    for _ in range(n_iter):
+        sirt_iteration(x, p, row_inv, col_inv, geom, angles, z0=z0, slab=slab, lam=lam,
+                       nonneg=nonneg, proj_tmp=proj_tmp, vol_tmp=vol_tmp)
+    return x

@@ -325,6 +325,78 @@ fdk_status fdk_filter_adjoint(const fdk_geometry* g, int32_t view0, int32_t nvie
                      stream);
 }
 
+namespace {
+// Voxels in the slab: nz_local * Ny * Nx (after the slab is validated).
+int64_t slab_voxels(const fdk_geometry* g, int32_t nz_local) {
+  return (int64_t)nz_local * g->ny * g->nx;
+}
+constexpr float kSirtFloor = 1e-3f;  // sums below this fraction of the largest one are raised to it
+}  // namespace
+
+fdk_status fdk_sirt_weights(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t z0,
+                            int32_t nz_local, fdk_slab_kind slab, float* row_inv, float* col_inv,
+                            float* vol_tmp, void* stream) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if ((st = check_views(g, view0, nviews))) return st;
+  if (nviews <= 0) return fail(FDK_ERR_INVALID_ARG, "SIRT needs at least one view");
+  if (!row_inv || !col_inv || !vol_tmp) return fail(FDK_ERR_INVALID_ARG, "SIRT buffer pointer is NULL");
+  if (col_inv == vol_tmp) return fail(FDK_ERR_INVALID_ARG, "col_inv and vol_tmp must differ");
+  const fdk::GeoConst gc = make_geo(g);
+  Slab sl;
+  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  const int64_t nproj = (int64_t)nviews * g->nu * g->nv, nvox = slab_voxels(g, nz_local);
+  int e = 0;
+  // Column sums B 1 (all-ones projections, held in row_inv for now).
+  if ((e = fdk::launch_fill(row_inv, nproj, 1.0f, stream)))
+    return fail(FDK_ERR_HIP, "fill failed: HIP error %d", e);
+  if ((st = fdk_backproject(g, view0, nviews, row_inv, FDK_F32, col_inv, z0, nz_local, slab, 1.0f,
+                            0, stream)))
+    return st;
+  // Row sums F 1.
+  if ((e = fdk::launch_fill(vol_tmp, nvox, 1.0f, stream)))
+    return fail(FDK_ERR_HIP, "fill failed: HIP error %d", e);
+  if ((st = fdk_forward_project(g, view0, nviews, vol_tmp, z0, nz_local, slab, row_inv, 1.0f, 0,
+                                stream)))
+    return st;
+  uint32_t* scratch = reinterpret_cast<uint32_t*>(vol_tmp);  // vol_tmp is free again
+  if ((e = fdk::launch_invert_floor(row_inv, nproj, kSirtFloor, scratch, stream)) ||
+      (e = fdk::launch_invert_floor(col_inv, nvox, kSirtFloor, scratch + 1, stream)))
+    return fail(FDK_ERR_HIP, "inversion failed: HIP error %d", e);
+  return ok();
+}
+
+fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int32_t nviews, const float* p,
+                              const float* row_inv, const float* col_inv, float* x, int32_t z0,
+                              int32_t nz_local, fdk_slab_kind slab, float lambda, uint32_t flags,
+                              float* proj_tmp, float* vol_tmp, void* stream) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if ((st = check_views(g, view0, nviews))) return st;
+  if (nviews <= 0) return fail(FDK_ERR_INVALID_ARG, "SIRT needs at least one view");
+  if (!p || !row_inv || !col_inv || !x || !proj_tmp || !vol_tmp)
+    return fail(FDK_ERR_INVALID_ARG, "SIRT buffer pointer is NULL");
+  if (proj_tmp == p || proj_tmp == row_inv || vol_tmp == x || vol_tmp == col_inv)
+    return fail(FDK_ERR_INVALID_ARG, "SIRT workspaces must not alias the inputs");
+  if (!std::isfinite(lambda)) return fail(FDK_ERR_INVALID_ARG, "lambda is not finite");
+  if (flags & ~FDK_NONNEG) return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  const fdk::GeoConst gc = make_geo(g);
+  Slab sl;
+  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  const int64_t nproj = (int64_t)nviews * g->nu * g->nv, nvox = slab_voxels(g, nz_local);
+  if ((st = fdk_forward_project(g, view0, nviews, x, z0, nz_local, slab, proj_tmp, 1.0f, 0, stream)))
+    return st;
+  int e = fdk::launch_sirt_residual(p, row_inv, proj_tmp, nproj, stream);
+  if (e) return fail(FDK_ERR_HIP, "residual failed: HIP error %d", e);
+  if ((st = fdk_backproject(g, view0, nviews, proj_tmp, FDK_F32, vol_tmp, z0, nz_local, slab, 1.0f,
+                            0, stream)))
+    return st;
+  e = fdk::launch_sirt_update(x, col_inv, vol_tmp, nvox, lambda, (flags & FDK_NONNEG) ? 1 : 0,
+                              stream);
+  if (e) return fail(FDK_ERR_HIP, "update failed: HIP error %d", e);
+  return ok();
+}
+
 fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local, fdk_slab_kind slab,
                          int32_t band[4]) {
   fdk_status st = check_geometry(g);

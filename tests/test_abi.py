@@ -203,3 +203,21 @@ def test_filter_adjoint_validation():
                                 None) == 1
     assert "overlap" in L.fdk_last_error().decode()
     assert L.fdk_filter_adjoint(None, 0, 4, FAKE, FAKE, 0, None) == 1
+
+
+def test_sirt_validation():
+    L = fdk.lib()
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    A, B_, C_, D_ = (C.c_void_p(0x1000 * k) for k in (1, 2, 3, 4))
+    assert L.fdk_sirt_weights(C.byref(cg), 0, 4, 0, 8, 0, None, B_, C_, None) == 1
+    assert "NULL" in L.fdk_last_error().decode()
+    assert L.fdk_sirt_weights(C.byref(cg), 0, 4, 0, 8, 0, A, B_, B_, None) == 1
+    assert L.fdk_sirt_weights(C.byref(cg), 0, 0, 0, 8, 0, A, B_, C_, None) == 1
+    assert L.fdk_sirt_weights(C.byref(cg), 0, 4, 4, 8, 0, A, B_, C_, None) == 1  # slab past Nz
+    E_, F_ = C.c_void_p(0x5000), C.c_void_p(0x6000)
+    it = L.fdk_sirt_iteration
+    assert it(C.byref(cg), 0, 4, A, B_, C_, D_, 0, 8, 0, 1.0, 0, A, F_, None) == 1
+    assert "alias" in L.fdk_last_error().decode()
+    assert it(C.byref(cg), 0, 4, A, B_, C_, D_, 0, 8, 0, float("nan"), 0, E_, F_, None) == 1
+    assert it(C.byref(cg), 0, 4, A, B_, C_, D_, 0, 8, 0, 1.0, 8, E_, F_, None) == 1
+    assert "flags" in L.fdk_last_error().decode()
