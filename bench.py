@@ -29,7 +29,9 @@ the back-projection launches' event time (the rate the paper reports) and,
 beside it, the whole pipeline's wall time. The default run adds one such
 pass to its line (--no-slab skips it), and the time of a SIRT iteration
 (forward projection, weighted residual, back-projection, update) at 256^3
-from 360 views of 384^2 (--no-sirt skips it).
+from 360 views of 384^2 (--no-sirt skips it), and the other workloads of the
+scan list (64^3 FDK, 512^3 back-projection, one forward and backward step on
+four 256^3 volumes; --no-configs skips them).
 """
 from __future__ import annotations
 
@@ -96,6 +98,8 @@ def parse():
     ap.add_argument("--no-16bit", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 64^3, 512^3 and differentiable 256^3 legs of the default run")
     ap.add_argument("--no-sirt", action="store_true",
                     help="skip the SIRT leg (256^3, 360 views) of the default run")
     ap.add_argument("--no-slab", action="store_true",
@@ -212,6 +216,78 @@ def run_sirt(dev, iters=10):
         f"({gups(ups, it_ms / 1e3):.1f} GUPS over both passes)")
     return {"sirt256_iter_ms": round(it_ms, 3), "sirt256_gups": round(gups(ups, it_ms / 1e3), 1),
             "sirt256_weights_ms": round(e0.elapsed_time(e1), 2)}
+
+
+def run_configs(dev):
+    """The other workloads of the scan list, each timed with HIP events on
+    the launch stream (inputs resident): the 64^3 FDK (filter and
+    back-projection), the 512^3 back-projection from 512 views, and one
+    training step (forward back-projection and matched backward) on the
+    batch of four 256^3 volumes from 360 views."""
+    import numpy as np
+    import torch
+
+    import paper_1909_02724_amd as fdk
+    import synth
+    import synth.gpu as sg
+
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    # 64^3 FDK from 64 views of 64^2, Ram-Lak
+    c = synth.config("fdk64")
+    g, ang = c["geom"], synth.angles(c["np"])
+    e = sg.phantom_project(g, ang, synth.ellipsoids(c["seed"], c["n_ell"], g), device=dev)
+    q = torch.empty_like(e)
+    vol = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=dev)
+    sc = fdk.fdk_scale(g, ang)
+
+    def fdk64():
+        fdk.filter(e, g, ang, kind="ramlak", out=q)
+        fdk.backproject(q, g, ang, out=vol, scale=sc)
+    ms = timed(fdk64, 20)
+    out["fdk64_ms"] = round(ms, 4)
+    out["fdk64_gups"] = round(gups(float(g.nx) * g.ny * g.nz * c["np"], ms / 1e3), 2)
+    # 512^3 back-projection from 512 views of 512^2
+    c = synth.config("bp512")
+    g, ang = c["geom"], synth.angles(c["np"])
+    e = sg.phantom_project(g, ang, synth.ellipsoids(c["seed"], c["n_ell"], g), device=dev)
+    q = fdk.filter(e, g, ang, kind=c["filter"])
+    del e
+    vol = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=dev)
+    ms = timed(lambda: fdk.backproject(q, g, ang, out=vol), 3)
+    out["bp512_ms"] = round(ms, 3)
+    out["bp512_gups"] = round(gups(float(g.nx) * g.ny * g.nz * c["np"], ms / 1e3), 1)
+    del q, vol
+    # differentiable batch: 4 x 256^3 from 360 views of 384^2, forward + backward
+    c = synth.config("diff256")
+    g, ang = c["geom"], synth.angles(c["np"])
+    rng = np.random.default_rng(c["seed"])
+    qb = torch.from_numpy(rng.standard_normal((c["batch"], c["np"], g.nv, g.nu),
+                                              dtype=np.float32)).to(dev).requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((c["batch"], g.nz, g.ny, g.nx),
+                                             dtype=np.float32)).to(dev)
+    scale = fdk.fdk_scale(g, ang)
+
+    def step():
+        qb.grad = None
+        (fdk.fdk_backprojection(qb, g, ang, scale) * w).sum().backward()
+    ms = timed(step, 3)
+    out["diff256_step_ms"] = round(ms, 2)
+    log(f"configs: fdk64 {out['fdk64_ms']} ms ({out['fdk64_gups']} GUPS), bp512 {out['bp512_ms']} ms "
+        f"({out['bp512_gups']} GUPS), diff256 forward+backward {out['diff256_step_ms']} ms")
+    return out
 
 
 def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic):
@@ -374,6 +450,9 @@ def main():
 
     if not args.no_sirt and args.workload == "bp2048":
         result_extra.update(run_sirt(dev))
+
+    if not args.no_configs and args.workload == "bp2048":
+        result_extra.update(run_configs(dev))
 
     if not args.no_slab and args.workload == "bp2048":
         del q32
