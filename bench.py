@@ -480,12 +480,27 @@ def main():
             oracle.backproject(g, ang[:nv_cpu], qc, voxels=vox)
             done += nvox * nv_cpu
         el = time.time() - t
-        cpu = {"value": round(gups(done, el), 5), "unit": "GUPS", "cores": oracle.num_threads(),
-               "kind": "oracle",
+        threads = oracle.num_threads()
+        # one thread, briefly, for the per-core rate
+        oracle.set_num_threads(1)
+        t1, done1 = time.time(), 0
+        while time.time() - t1 < args.cpu_seconds / 3:
+            oracle.backproject(g, ang[:nv_cpu], qc, voxels=vox[:1024])
+            done1 += 1024 * nv_cpu
+        el1 = time.time() - t1
+        oracle.set_num_threads(threads)
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
+                      if ln.startswith("model name")), "unknown")
+        rate = gups(done, el)
+        cpu = {"value": round(rate, 5), "unit": "GUPS", "cores": threads, "kind": "oracle",
                "sample": f"{done} voxel-view updates ({nvox} random voxels of the "
                          f"{g.nx}x{g.ny}x{g.nz} volume x {nv_cpu} views of {g.nv}x{g.nu}, "
-                         f"repeated for {el:.1f} s)"}
-        log(f"cpu oracle: {cpu['value']} GUPS on {cpu['cores']} threads")
+                         f"repeated for {el:.1f} s)",
+               "single_thread_gups": round(gups(done1, el1), 5),
+               "cpu_model": model, "host_cpus": os.cpu_count(),
+               "extrapolated_full_step_s": round(updates / (rate * 2 ** 30), 0)}
+        log(f"cpu oracle: {cpu['value']} GUPS on {threads} threads, {cpu['single_thread_gups']} on one "
+            f"({model}); a full step would take ~{cpu['extrapolated_full_step_s']:.0f} s")
 
     out = {
         "metric": METRIC, "value": round(gups32, 2), "unit": "GUPS", "n_gpus": 1,

@@ -56,6 +56,8 @@ def lib():
             build()
         L = C.CDLL(_LIB)
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
+        L.or_set_num_threads.restype = None
         L.or_projection_matrix.argtypes = [_DP, C.c_double, _DP]
         L.or_projection_matrix4.argtypes = [_DP, C.c_double, _DP]
         L.or_m0.argtypes = [_DP, _DP]
@@ -108,6 +110,10 @@ def gvec(geom) -> np.ndarray:
     return np.array([geom.nx, geom.ny, geom.nz, geom.dx, geom.dy, geom.dz,
                      geom.nu, geom.nv, geom.du, geom.dv, geom.off_u, geom.off_v,
                      geom.sod, geom.sdd], dtype=np.float64)
+
+
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(int(n))
 
 
 def num_threads() -> int:

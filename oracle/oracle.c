@@ -53,6 +53,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Threads later parallel loops use (for timing the oracle on one core). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Geometry: Eq. (2), the projection matrix as the literal product      */
 /* M1 * Mrot * M0 of 4x4 matrices, first three rows kept (3x4).         */
