@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "fdk_internal.h"
+#include "ops_internal.h"
 
 namespace {
 

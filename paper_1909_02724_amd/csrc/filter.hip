@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "geom_device.h"
+#include "ops_internal.h"
 
 namespace fdk {
 namespace {

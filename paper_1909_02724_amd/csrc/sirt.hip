@@ -7,7 +7,7 @@
 #include <algorithm>
 #include <cstdint>
 
-#include "fdk_internal.h"
+#include "ops_internal.h"
 
 namespace fdk {
 namespace {
