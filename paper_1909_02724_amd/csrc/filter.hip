@@ -29,6 +29,7 @@ constexpr int kFftMaxL = 1 << kFftMaxLog;
 constexpr int kFftPerThread = kFftMaxL / kFilterThreads;
 constexpr int kFftRowPairs = 8;            // row pairs per workgroup (one H each)
 constexpr int kDirectMaxNu = 256;          // below this the direct kernel is cheaper
+constexpr int kDirectBlock = 128;          // taps per partial sum in the direct kernel
 
 // Ramp kernel h(n) at sample pitch tau: Ram-Lak (band-limited ramp) or
 // Shepp-Logan (ramp times sinc), FDK literature forms.
@@ -93,10 +94,17 @@ __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
   __syncthreads();
   OutT* qr = q + br.qout;
   for (int32_t a = threadIdx.x; a < nu; a += kFilterThreads) {
+    // Blocked sum: a serial FP32 sum over up to 8192 taps loses about
+    // 1e-5 relative; partial sums of kDirectBlock taps keep it near 2e-7.
     float acc = 0.0f;
-    for (int32_t n = 0; n < nu; ++n) {
-      const int32_t d = a - n;
-      acc = fmaf(h[d < 0 ? -d : d], et[n], acc);
+    for (int32_t n0 = 0; n0 < nu; n0 += kDirectBlock) {
+      const int32_t n1 = min(nu, n0 + kDirectBlock);
+      float part = 0.0f;
+      for (int32_t n = n0; n < n1; ++n) {
+        const int32_t d = a - n;
+        part = fmaf(h[d < 0 ? -d : d], et[n], part);
+      }
+      acc += part;
     }
     store_q(qr + a, ADJ ? acc * cos_weight(gc, du, dv, sdd, a, b) : acc);
   }

@@ -422,3 +422,62 @@ def test_sirt_matches_oracle(nonneg):
         r = host(gpu(p)) - host(fdk.forward_project(xk, g, ang))
         res.append(float(np.sum(Rr * r * r)))
     assert res[0] > res[1] > res[2]
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 2), (17, 1, 5), (33, 16, 1)])
+def test_degenerate_volumes(shape):
+    """Volumes thinner than a brick in one or more directions (partial
+    bricks only, a single slice, a single column) against the oracle, both
+    directions of the pair."""
+    nx, ny, nz = shape
+    g = BASE.replace(nx=nx, ny=ny, nz=nz, nu=24, nv=20, sod=60.0, sdd=120.0)
+    ang = synth.angles(7, start=0.05)
+    q = synth.random_projections(51, 7, g)
+    vol = host(fdk.backproject(gpu(q), g, ang))
+    assert rel_l2(vol, oracle.backproject(g, ang, q.astype(np.float64))) <= 1e-5
+    x = np.random.default_rng(52).standard_normal((nz, ny, nx)).astype(np.float32)
+    fp = host(fdk.forward_project(gpu(x), g, ang))
+    assert rel_l2(fp, oracle.forward_project(g, ang, x.astype(np.float64))) <= 1e-5
+
+
+def test_single_view_and_axis_angles():
+    """One view per call, at gantry angles where sin or cos is exactly 0 or
+    +-1, accumulated call by call."""
+    g = BASE.replace(nz=12)
+    ang = np.array([0.0, math.pi / 2, math.pi, 3 * math.pi / 2, 0.25])
+    q = synth.random_projections(53, len(ang), g)
+    out = None
+    for s in range(len(ang)):
+        out = fdk.backproject(gpu(q[s:s + 1]), g, ang, view0=s, out=out, accumulate=s > 0)
+    ref = oracle.backproject(g, ang, q.astype(np.float64))
+    assert rel_l2(host(out), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("du,off_u", [(1.0, 3900.0), (0.05, 0.0)])
+def test_wide_detector(du, off_u):
+    """8192-pixel rows, the widest the filter takes: a footprint near the
+    row's end (tiled back-projector) and one too wide for the LDS tiles
+    (direct back-projector), both directions of the pair."""
+    g = BASE.replace(nx=48, ny=40, nz=8, nu=8192, nv=6, du=du, dv=6.0, off_u=off_u,
+                     sod=400.0, sdd=800.0)
+    ang = synth.angles(5, start=0.3)
+    q = synth.random_projections(54, 5, g)
+    vol = host(fdk.backproject(gpu(q), g, ang))
+    assert rel_l2(vol, oracle.backproject(g, ang, q.astype(np.float64))) <= 1e-5
+    x = np.random.default_rng(56).standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
+    fp = host(fdk.forward_project(gpu(x), g, ang))
+    assert rel_l2(fp, oracle.forward_project(g, ang, x.astype(np.float64))) <= 1e-5
+
+
+@pytest.mark.parametrize("nu", [5000, 8192])
+def test_direct_filter_beyond_fft_limit(nu):
+    """Rows above 4096 pixels exceed the 8192-point FFT and take the direct
+    convolution, whose blocked FP32 sum holds the 1e-5 bar up to 8192."""
+    g = BASE.replace(nu=nu, nv=3, sod=4.0 * nu, sdd=8.0 * nu)
+    ang = synth.angles(2)
+    e = np.random.default_rng(55).uniform(0, 10, (2, g.nv, g.nu)).astype(np.float32)
+    got = host(fdk.filter(gpu(e), g, ang, kind="shepp-logan"))
+    ref = oracle.filter(g, e.astype(np.float64), "shepp-logan")
+    err = rel_l2(got, ref)
+    announce(f"  direct filter nu={nu}: rel-L2 {err:.3e}")
+    assert err <= 1e-5

@@ -131,6 +131,7 @@ def test_diff256_autograd_checks():
     torch.cuda.synchronize()
     # Zero-mean data: the inner products cancel, so mismatches are measured
     # against the Cauchy-Schwarz scale |B q| |w| + |q| |F w|.
+    vol = vol.detach()
     for b in range(B):
         lhs = float((vol[b].double() * w[b].double()).sum())
         rhs = float((q[b].detach().double() * q.grad[b].double()).sum())
