@@ -102,6 +102,8 @@ def parse():
                     help="skip the 64^3, 512^3 and differentiable 256^3 legs of the default run")
     ap.add_argument("--no-sirt", action="store_true",
                     help="skip the SIRT leg (256^3, 360 views) of the default run")
+    ap.add_argument("--no-filter", action="store_true",
+                    help="skip the filtering leg (2048- and 4096-pixel rows) of the default run")
     ap.add_argument("--no-slab", action="store_true",
                     help="skip the streamed 4096^2-slab leg of the default run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -290,6 +292,48 @@ def run_configs(dev):
     return out
 
 
+def run_filter(dev):
+    """The filtering stage alone (cosine weight and Shepp-Logan ramp), HBM
+    resident in and out, timed with HIP events on the launch stream: 256
+    views of 2048^2 (FP32 to FP32, 4096-point FFTs) and the slab
+    reconstruction's rows, 256 views x 578 rows of 4096 (FP32 to FP16,
+    8192-point FFTs). Algorithmic bytes: one read of each input pixel and one
+    write of each output pixel."""
+    import torch
+
+    import paper_1909_02724_amd as fdk
+    import synth
+
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for name, nu, nv, dt, ob in (("filter2048", 2048, 2048, torch.float32, 4),
+                                 ("filter4096", 4096, 578, torch.float16, 2)):
+        g = synth.Geom(nx=64, ny=64, nz=64, nu=nu, nv=nv, sod=1.0e3, sdd=1.5e3, du=1.0, dv=1.0)
+        nviews = 256
+        ang = synth.angles(nviews)
+        e = torch.empty((nviews, nv, nu), dtype=torch.float32, device=dev).uniform_(0.0, 4.0)
+        q = torch.empty((nviews, nv, nu), dtype=dt, device=dev)
+        fdk.filter(e, g, ang, kind="shepp-logan", out=q)
+        torch.cuda.synchronize()
+        reps = 3
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fdk.filter(e, g, ang, kind="shepp-logan", out=q)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        gbs = float(nviews) * nv * nu * (4 + ob) / (ms / 1e3) / 1e9
+        out[f"{name}_ms"] = round(ms, 3)
+        out[f"{name}_GBps"] = round(gbs, 1)
+        out[f"{name}_hbm_frac"] = round(gbs / (HBM_PEAK / 1e9), 4)
+        log(f"{name}: {nviews} views of {nv}x{nu} in {ms:.2f} ms, {gbs:.0f} GB/s "
+            f"({gbs / (HBM_PEAK / 1e9):.3f} of HBM peak)")
+        del e, q
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic):
     per_launch_s = ms_step / 1e3 / launches
     updates_per_launch = updates / launches
@@ -383,7 +427,7 @@ def main():
     t0 = time.time()
     ell = synth.ellipsoids(cfg["seed"], cfg["n_ell"], g)
     q32 = torch.empty((n_views, g.nv, g.nu), dtype=torch.float32, device=dev)
-    chunk = 64
+    chunk = 256  # the filtering leg's launch size too
     e = torch.empty((chunk, g.nv, g.nu), dtype=torch.float32, device=dev)
     for s in range(0, n_views, chunk):
         n = min(chunk, n_views - s)
@@ -453,6 +497,9 @@ def main():
 
     if not args.no_configs and args.workload == "bp2048":
         result_extra.update(run_configs(dev))
+
+    if not args.no_filter and args.workload == "bp2048":
+        result_extra.update(run_filter(dev))
 
     if not args.no_slab and args.workload == "bp2048":
         del q32

@@ -7,15 +7,17 @@
 // Short rows (and rows too long for the FFT tile) use a direct convolution:
 // one workgroup per row, the weighted row and the kernel taps in LDS.
 //
-// Longer rows use the convolution theorem (Sec. 2.2.3) with FFTs in LDS:
-// rows are zero-padded to L >= 2 Nu - 1 (a power of two), so the circular
+// Longer rows use the convolution theorem (Sec. 2.2.3): rows are
+// zero-padded to L >= 2 Nu - 1 (a power of two), so the circular
 // convolution of length L equals the linear one on the Nu outputs. Two rows
 // travel as the real and imaginary parts of one complex sequence: the ramp
 // kernel is real and even, its spectrum H is real, and IFFT(FFT(a + i b) H) =
-// (a * h) + i (b * h). Each workgroup computes H once (an FFT of the
-// circularly arranged taps) and then filters several row pairs. In-place
-// radix-2 decimation in time on bit-reversed input; twiddles in LDS.
+// (a * h) + i (b * h). The FFTs are radix-16 Stockham passes over points held
+// in registers, exchanged through LDS between passes; each workgroup computes
+// H once and then loops over row pairs.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "geom_device.h"
 #include "ops_internal.h"
@@ -24,10 +26,8 @@ namespace fdk {
 namespace {
 
 constexpr int kFilterThreads = 256;
-constexpr int kFftMaxLog = 13;             // L <= 8192 complex points (64 KB)
-constexpr int kFftMaxL = 1 << kFftMaxLog;
-constexpr int kFftPerThread = kFftMaxL / kFilterThreads;
-constexpr int kFftRowPairs = 8;            // row pairs per workgroup (one H each)
+constexpr int kFftMaxLog = 13;             // L <= 8192 complex points (68 KB of LDS)
+constexpr int64_t kFftMaxGroups = 2048;    // workgroups of an FFT launch
 constexpr int kDirectMaxNu = 256;          // below this the direct kernel is cheaper
 constexpr int kDirectBlock = 128;          // taps per partial sum in the direct kernel
 
@@ -110,136 +110,398 @@ __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
   }
 }
 
-// In-place radix-2 FFT of x[0, L) (bit-reversed input, natural output),
-// forward transform exp(-2 pi i k n / L); tw[k] = exp(-2 pi i k / L), k < L/2.
-__device__ void fft_inplace(float2* x, const float2* tw, int32_t logl) {
-  const int32_t L = 1 << logl, halfL = L >> 1;
-  for (int32_t s = 1; s <= logl; ++s) {
-    const int32_t half = 1 << (s - 1);
-    const int32_t tstep = L >> s;  // twiddle index stride for this stage
-    for (int32_t bf = threadIdx.x; bf < halfL; bf += kFilterThreads) {
-      const int32_t pos = bf & (half - 1);
-      const int32_t i = ((bf >> (s - 1)) << s) + pos;
-      const int32_t j = i + half;
-      const float2 w = tw[pos * tstep];
-      const float2 u = x[i], v = x[j];
-      const float2 t = make_float2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
-      x[i] = make_float2(u.x + t.x, u.y + t.y);
-      x[j] = make_float2(u.x - t.x, u.y - t.y);
-    }
-    __syncthreads();
+// ---- FFT path -------------------------------------------------------------
+// Stockham FFT of L = 2^LOGL points: every thread holds 16 points in
+// registers; a pass gathers R points strided by L/R, applies the twiddles
+// W^(r k), runs an R-point DFT in registers and scatters the results to their
+// autosorted places, through one padded LDS buffer per FFT. Passes are radix
+// 16, plus one first pass of radix 2, 4 or 8 when LOGL is not a multiple of
+// four (that pass needs no twiddles). The forward transform's first pass
+// reads the rows from global memory, the inverse transform's last pass writes
+// them, so a row pair crosses LDS 2 P - 1 times for P passes.
+template <int LOGL>
+struct FftCfg {
+  static constexpr int L = 1 << LOGL;
+  static constexpr int TPF = L / 16;                 // threads per FFT
+  static constexpr int WG = TPF > 256 ? TPF : 256;   // threads per workgroup
+  static constexpr int G = WG / TPF;                 // FFTs in flight per workgroup
+  static constexpr int RR = 1 << (LOGL % 4);         // first-pass radix (1: none)
+  static constexpr int NP = (RR > 1 ? 1 : 0) + LOGL / 4;  // passes
+  static constexpr int BUF = L + L / 16;             // padded points per FFT
+};
+
+template <int LOGL, int IP>
+struct PassCfg {
+  using C = FftCfg<LOGL>;
+  static constexpr bool kRR = C::RR > 1 && IP == 0;
+  static constexpr int R = kRR ? C::RR : 16;
+  static constexpr int NS = IP == 0 ? 1 : (C::RR > 1 ? C::RR : 16) << (4 * (IP - 1));
+  static constexpr int B = 16 / R;  // butterflies per thread
+};
+
+// One padding point after every 16 keeps the radix-16 scatters free of bank
+// conflicts.
+__device__ __forceinline__ int32_t fpad(int32_t i) { return i + (i >> 4); }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// x W16^q with W16 = exp(-2 pi i / 16), q in [0, 8): exact rotations by
+// multiples of pi/2 and pi/4 use adds only.
+__device__ __forceinline__ float2 rot16(float2 x, int q) {
+  constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+  constexpr float h = 0.70710678118654752440f;   // sqrt(1/2)
+  switch (q) {
+    case 0: return x;
+    case 1: return make_float2(fmaf(x.x, c1, x.y * s1), fmaf(x.y, c1, -x.x * s1));
+    case 2: return make_float2((x.x + x.y) * h, (x.y - x.x) * h);
+    case 3: return make_float2(fmaf(x.x, s1, x.y * c1), fmaf(x.y, s1, -x.x * c1));
+    case 4: return make_float2(x.y, -x.x);
+    case 5: return make_float2(fmaf(x.y, c1, -x.x * s1), -fmaf(x.x, c1, x.y * s1));
+    case 6: return make_float2((x.y - x.x) * h, -(x.x + x.y) * h);
+    default: return make_float2(fmaf(x.y, s1, -x.x * c1), -fmaf(x.x, s1, x.y * c1));
   }
 }
 
-__device__ __forceinline__ int32_t bitrev(int32_t n, int32_t logl) {
-  return static_cast<int32_t>(__builtin_bitreverse32(static_cast<uint32_t>(n)) >> (32 - logl));
+// In-register DFT of v[0, N), N in {2, 4, 8, 16}, natural order in and out:
+// radix-2 decimation in time on the bit-reversed copy.
+template <int N>
+__device__ __forceinline__ void dft_reg(float2* v) {
+  constexpr int LOGN = N == 2 ? 1 : N == 4 ? 2 : N == 8 ? 3 : 4;
+  float2 a[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0; b < LOGN; ++b) r |= ((i >> b) & 1) << (LOGN - 1 - b);
+    a[r] = v[i];
+  }
+#pragma unroll
+  for (int h = 1; h < N; h *= 2) {
+#pragma unroll
+    for (int i = 0; i < N; i += 2 * h) {
+#pragma unroll
+      for (int p = 0; p < h; ++p) {
+        const float2 t = rot16(a[i + p + h], p * (16 / (2 * h)));
+        const float2 u = a[i + p];
+        a[i + p] = make_float2(u.x + t.x, u.y + t.y);
+        a[i + p + h] = make_float2(u.x - t.x, u.y - t.y);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = a[i];
 }
 
-template <typename OutT, bool ADJ>
-__global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(
-    GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
-    int32_t logl, int64_t nrows, const float* __restrict__ e, OutT* __restrict__ q) {
-  extern __shared__ float2 flds[];
-  const int32_t L = 1 << logl, nu = gc.nu;
-  float2* x = flds;       // L complex points
-  float2* tw = flds + L;  // L / 2 twiddles
-  for (int32_t k = threadIdx.x; k < L / 2; k += kFilterThreads) {
+// Base twiddles W^(k 2^b), b < 4, of the radix-16 pass IP for thread t,
+// W = exp(-2 pi i / L), k = (t mod NS) L / (16 NS); rounded from FP64.
+template <int LOGL, int IP>
+__device__ __forceinline__ void pass_twiddles(int32_t t, float2* w) {
+  using P = PassCfg<LOGL, IP>;
+  const int32_t k = (t % P::NS) * (FftCfg<LOGL>::L / (16 * P::NS));
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
     double sv, cv;
-    sincospi(-2.0 * k / L, &sv, &cv);
-    tw[k] = make_float2(static_cast<float>(cv), static_cast<float>(sv));
+    sincospi(-2.0 * static_cast<double>(k << b) / FftCfg<LOGL>::L, &sv, &cv);
+    w[b] = make_float2(static_cast<float>(cv), static_cast<float>(sv));
   }
-  // Kernel spectrum: taps tau * h(n) for |n| < Nu arranged circularly.
-  for (int32_t n = threadIdx.x; n < L; n += kFilterThreads) {
-    const int32_t m = n < L / 2 ? n : n - L;  // signed offset
-    const float hv = (m > -nu && m < nu) ? static_cast<float>(tau * ramp_tap(kind, m, tau)) : 0.0f;
-    x[bitrev(n, logl)] = make_float2(hv, 0.0f);
-  }
-  __syncthreads();
-  fft_inplace(x, tw, logl);
-  float H[kFftPerThread];
-#pragma unroll
-  for (int m = 0; m < kFftPerThread; ++m) {
-    const int32_t k = threadIdx.x + m * kFilterThreads;
-    H[m] = (k < L) ? x[k].x / static_cast<float>(L) : 0.0f;  // real; 1/L of the inverse folded in
-  }
-  __syncthreads();
+}
 
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 2 * kFftRowPairs;  // launch rows
-  for (int32_t p = 0; p < kFftRowPairs; ++p) {
-    const int64_t ra = row0 + 2 * p, rb = ra + 1;
-    if (ra >= nrows) break;  // uniform
-    const bool has_b = rb < nrows;
-    const BandRow rowa = band_row(rband, nu, ra);
-    const BandRow rowb = band_row(rband, nu, has_b ? rb : ra);
-    for (int32_t n = threadIdx.x; n < L; n += kFilterThreads) {
-      float re = 0.0f, im = 0.0f;
-      if (n < nu) {
-        re = ADJ ? e[rowa.ein + n] : e[rowa.ein + n] * cos_weight(gc, du, dv, sdd, n, rowa.b);
-        if (has_b)
-          im = ADJ ? e[rowb.ein + n] : e[rowb.ein + n] * cos_weight(gc, du, dv, sdd, n, rowb.b);
-      }
-      x[bitrev(n, logl)] = make_float2(re, im);
-    }
-    __syncthreads();
-    fft_inplace(x, tw, logl);
-    // Multiply by H, conjugate, and write back bit-reversed: the forward
-    // transform of the conjugate is L times the conjugated inverse.
-    float2 y[kFftPerThread];
+// v[r] *= W^(r k) for r in [1, 16), from the base twiddles (at most three
+// products deep).
+__device__ __forceinline__ void apply_twiddles(float2* v, const float2* w) {
+  const float2 w1 = w[0], w2 = w[1], w4 = w[2], w8 = w[3];
+  const float2 w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+  v[1] = cmul(v[1], w1);
+  v[2] = cmul(v[2], w2);
+  v[3] = cmul(v[3], w3);
+  v[4] = cmul(v[4], w4);
+  v[5] = cmul(v[5], w5);
+  v[6] = cmul(v[6], w6);
+  v[7] = cmul(v[7], w7);
+  v[8] = cmul(v[8], w8);
+  v[9] = cmul(v[9], cmul(w1, w8));
+  v[10] = cmul(v[10], cmul(w2, w8));
+  v[11] = cmul(v[11], cmul(w3, w8));
+  v[12] = cmul(v[12], cmul(w4, w8));
+  v[13] = cmul(v[13], cmul(w5, w8));
+  v[14] = cmul(v[14], cmul(w6, w8));
+  v[15] = cmul(v[15], cmul(w7, w8));
+}
+
+// Input index of point (m, r) of pass IP for thread t: butterfly
+// j = t + m TPF, element r, index j + r L / R.
+template <int LOGL, int IP>
+__device__ __forceinline__ int32_t gather_index(int32_t t, int m, int r) {
+  using P = PassCfg<LOGL, IP>;
+  return t + m * FftCfg<LOGL>::TPF + r * (FftCfg<LOGL>::L / P::R);
+}
+
+// Output index of result r of butterfly j in pass IP (Stockham autosort).
+template <int LOGL, int IP>
+__device__ __forceinline__ int32_t scatter_index(int32_t j, int r) {
+  using P = PassCfg<LOGL, IP>;
+  return (j / P::NS) * (P::NS * P::R) + (j % P::NS) + r * P::NS;
+}
+
+// Twiddle, DFT and scatter of pass IP; v holds the gathered points.
+template <int LOGL, int IP>
+__device__ __forceinline__ void pass_compute(float2* v, const float2 (*tw)[4]) {
+  using P = PassCfg<LOGL, IP>;
+  if constexpr (P::NS > 1) apply_twiddles(v, tw[IP]);
 #pragma unroll
-    for (int m = 0; m < kFftPerThread; ++m) {
-      const int32_t k = threadIdx.x + m * kFilterThreads;
-      if (k < L) {
-        const float2 v = x[k];
-        y[m] = make_float2(v.x * H[m], -v.y * H[m]);
-      }
-    }
-    __syncthreads();
+  for (int m = 0; m < P::B; ++m) dft_reg<P::R>(v + m * P::R);
+}
+
+template <int LOGL, int IP>
+__device__ __forceinline__ void pass_scatter_lds(float2* buf, int32_t t, const float2* v) {
+  using P = PassCfg<LOGL, IP>;
 #pragma unroll
-    for (int m = 0; m < kFftPerThread; ++m) {
-      const int32_t k = threadIdx.x + m * kFilterThreads;
-      if (k < L) x[bitrev(k, logl)] = y[m];
-    }
+  for (int m = 0; m < P::B; ++m)
+#pragma unroll
+    for (int r = 0; r < P::R; ++r)
+      buf[fpad(scatter_index<LOGL, IP>(t + m * FftCfg<LOGL>::TPF, r))] = v[m * P::R + r];
+}
+
+template <int LOGL, int IP>
+__device__ __forceinline__ void pass_gather_lds(const float2* buf, int32_t t, float2* v) {
+  using P = PassCfg<LOGL, IP>;
+#pragma unroll
+  for (int m = 0; m < P::B; ++m)
+#pragma unroll
+    for (int r = 0; r < P::R; ++r) v[m * P::R + r] = buf[fpad(gather_index<LOGL, IP>(t, m, r))];
+}
+
+// Passes IP..NP-1 of a transform whose points sit in v (already gathered
+// for pass IP). The last pass leaves its results in v, in the order of
+// scatter_index; every earlier pass crosses LDS.
+template <int LOGL, int IP>
+__device__ __forceinline__ void fft_rest(float2* buf, int32_t t, float2* v, const float2 (*tw)[4]) {
+  pass_compute<LOGL, IP>(v, tw);
+  if constexpr (IP + 1 < FftCfg<LOGL>::NP) {
+    __syncthreads();  // the buffer's previous contents are read
+    pass_scatter_lds<LOGL, IP>(buf, t, v);
     __syncthreads();
-    fft_inplace(x, tw, logl);
-    for (int32_t n = threadIdx.x; n < nu; n += kFilterThreads) {
-      const float2 v = x[n];
-      if (ADJ) {
-        store_q(q + rowa.qout + n, v.x * cos_weight(gc, du, dv, sdd, n, rowa.b));
-        if (has_b) store_q(q + rowb.qout + n, -v.y * cos_weight(gc, du, dv, sdd, n, rowb.b));
-      } else {
-        store_q(q + rowa.qout + n, v.x);
-        if (has_b) store_q(q + rowb.qout + n, -v.y);
-      }
-    }
-    __syncthreads();
+    pass_gather_lds<LOGL, IP + 1>(buf, t, v);
+    fft_rest<LOGL, IP + 1>(buf, t, v, tw);
   }
+}
+
+// Cosine weight of pixel a on a row: D rsqrt(D^2 + ((b - cv) dv)^2 + ((a - cu) du)^2),
+// the row's share precomputed.
+struct RowWeight {
+  float d, base;
+};
+__device__ __forceinline__ RowWeight row_weight(const GeoConst& gc, double dv, double sdd, int32_t b) {
+  const double bb = (b - gc.cv) * dv;
+  return RowWeight{static_cast<float>(sdd), static_cast<float>(sdd * sdd + bb * bb)};
+}
+__device__ __forceinline__ float pixel_weight(RowWeight rw, float cu, float du, int32_t a) {
+  const float x = (static_cast<float>(a) - cu) * du;
+  return rw.d * __frsqrt_rn(fmaf(x, x, rw.base));
+}
+
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer descriptor, gfx9 family
+
+// Raw buffer over `bytes` bytes from p: loads beyond return zero, stores
+// beyond are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
+                                           kBufferWord3);
+}
+__device__ __forceinline__ void buf_store_q(float x, __amdgpu_buffer_rsrc_t r, uint32_t off, float*) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store_q(float x, __amdgpu_buffer_rsrc_t r, uint32_t off, f16_t*) {
+  f16_t h;
+  store_q(&h, x);
+  __builtin_amdgcn_raw_buffer_store_b16(h.bits, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store_q(float x, __amdgpu_buffer_rsrc_t r, uint32_t off, bf16_t*) {
+  bf16_t h;
+  store_q(&h, x);
+  __builtin_amdgcn_raw_buffer_store_b16(h.bits, r, off, 0, 0);
+}
+
+// Rows travel in pairs, a as the real and b as the imaginary part of one
+// complex sequence; the spectrum of the kernel is real, so
+// IFFT(FFT(a + i b) H) = a * h + i b * h. The inverse is the forward
+// transform of the conjugate, conjugated, with 1/L folded into H.
+template <int LOGL, typename OutT, bool ADJ>
+__global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
+    GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
+    int64_t nrows, const float* __restrict__ e, OutT* __restrict__ q) {
+  using C = FftCfg<LOGL>;
+  constexpr int P0R = PassCfg<LOGL, 0>::R;
+  extern __shared__ float2 fbuf[];
+  const int32_t g = static_cast<int32_t>(threadIdx.x) / C::TPF;
+  const int32_t t = static_cast<int32_t>(threadIdx.x) % C::TPF;
+  float2* buf = fbuf + g * C::BUF;
+  const int32_t nu = gc.nu;
+  const float cuf = static_cast<float>(gc.cu), duf = static_cast<float>(du);
+
+  float2 tw[C::NP][4];
+#pragma unroll
+  for (int ip = 0; ip < C::NP; ++ip) tw[ip][0] = tw[ip][1] = tw[ip][2] = tw[ip][3] = make_float2(1.0f, 0.0f);
+  if constexpr (C::NP > 1) pass_twiddles<LOGL, 1>(t, tw[1]);
+  if constexpr (C::NP > 2) pass_twiddles<LOGL, 2>(t, tw[2]);
+  if constexpr (C::NP > 3) pass_twiddles<LOGL, 3>(t, tw[3]);
+  // The first pass never needs twiddles (NS = 1).
+
+  // Kernel spectrum: FFT of the taps tau h(m), |m| < Nu, placed circularly;
+  // each thread keeps H at the points it gathers in the inverse's first pass.
+  float2 v[16];
+#pragma unroll
+  for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
+#pragma unroll
+    for (int r = 0; r < P0R; ++r) {
+      const int32_t n = gather_index<LOGL, 0>(t, m, r);
+      const int32_t s = n < C::L / 2 ? n : n - C::L;
+      const float hv = (s > -nu && s < nu) ? static_cast<float>(tau * ramp_tap(kind, s, tau)) : 0.0f;
+      v[m * P0R + r] = make_float2(hv, 0.0f);
+    }
+  fft_rest<LOGL, 0>(buf, t, v, tw);
+  __syncthreads();
+  pass_scatter_lds<LOGL, C::NP - 1>(buf, t, v);
+  __syncthreads();
+  float H[16];
+  {
+    constexpr float inv_l = 1.0f / static_cast<float>(C::L);
+#pragma unroll
+    for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
+#pragma unroll
+      for (int r = 0; r < P0R; ++r) H[m * P0R + r] = buf[fpad(gather_index<LOGL, 0>(t, m, r))].x * inv_l;
+  }
+
+  // Row pairs are wave-uniform (an FFT spans whole waves), so each row is
+  // addressed through a buffer descriptor: pixels at or beyond Nu, and rows
+  // past the end, read as zero and are never written.
+  const int32_t gw = __builtin_amdgcn_readfirstlane(g);
+  const uint32_t npairs = static_cast<uint32_t>((nrows + 1) / 2);
+  const uint32_t band = static_cast<uint32_t>(rband.band);
+  for (uint32_t base = blockIdx.x * C::G; base < npairs; base += gridDim.x * C::G) {
+    const uint32_t pr = base + static_cast<uint32_t>(gw);
+    const uint32_t ra = 2 * pr, rb = ra + 1;
+    const bool has_a = pr < npairs, has_b = rb < static_cast<uint32_t>(nrows);
+    const uint32_t sa = ra / band, sb = rb / band;
+    const int32_t ba = rband.v0 + static_cast<int32_t>(ra - sa * band);
+    const int32_t bb = rband.v0 + static_cast<int32_t>(rb - sb * band);
+    const int64_t rowa_in = sa * rband.e_stride + static_cast<int64_t>(ra - sa * band) * nu;
+    const int64_t rowb_in = sb * rband.e_stride + static_cast<int64_t>(rb - sb * band) * nu;
+    const int64_t rowa_out = sa * rband.q_stride + static_cast<int64_t>(ra - sa * band) * nu;
+    const int64_t rowb_out = sb * rband.q_stride + static_cast<int64_t>(rb - sb * band) * nu;
+    const __amdgpu_buffer_rsrc_t ia = row_rsrc(e + (has_a ? rowa_in : 0), has_a ? nu * 4u : 0u);
+    const __amdgpu_buffer_rsrc_t ib = row_rsrc(e + (has_b ? rowb_in : 0), has_b ? nu * 4u : 0u);
+    const RowWeight wa = row_weight(gc, dv, sdd, ba), wb = row_weight(gc, dv, sdd, bb);
+
+    // Forward transform; its first pass reads (and weights) the two rows.
+    // Points in the upper half (index >= L/2 >= Nu) are padding.
+#pragma unroll
+    for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
+#pragma unroll
+      for (int r = 0; r < P0R; ++r) {
+        float re = 0.0f, im = 0.0f;
+        if (r < P0R / 2) {
+          const int32_t n = gather_index<LOGL, 0>(t, m, r);
+          const uint32_t off = static_cast<uint32_t>(n) * 4u;
+          re = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ia, off, 0, 0));
+          im = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ib, off, 0, 0));
+          if (!ADJ) {
+            re *= pixel_weight(wa, cuf, duf, n);
+            im *= pixel_weight(wb, cuf, duf, n);
+          }
+        }
+        v[m * P0R + r] = make_float2(re, im);
+      }
+    __syncthreads();  // the previous pair's last gather is done
+    fft_rest<LOGL, 0>(buf, t, v, tw);
+    __syncthreads();
+    pass_scatter_lds<LOGL, C::NP - 1>(buf, t, v);
+    __syncthreads();
+    // Inverse: conj(X) H gathered for the first pass.
+    pass_gather_lds<LOGL, 0>(buf, t, v);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = make_float2(v[i].x * H[i], -v[i].y * H[i]);
+    fft_rest<LOGL, 0>(buf, t, v, tw);
+    // The last pass has one radix-16 butterfly per thread (j = t, NS = L/16):
+    // result r is point t + r L/16, so the stores are coalesced; only the
+    // lower half (r < 8) holds row pixels.
+    const __amdgpu_buffer_rsrc_t oa =
+        row_rsrc(q + (has_a ? rowa_out : 0), has_a ? nu * static_cast<uint32_t>(sizeof(OutT)) : 0u);
+    const __amdgpu_buffer_rsrc_t ob =
+        row_rsrc(q + (has_b ? rowb_out : 0), has_b ? nu * static_cast<uint32_t>(sizeof(OutT)) : 0u);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int32_t n = scatter_index<LOGL, C::NP - 1>(t, r);
+      float ya = v[r].x, yb = -v[r].y;
+      if (ADJ) {
+        ya *= pixel_weight(wa, cuf, duf, n);
+        yb *= pixel_weight(wb, cuf, duf, n);
+      }
+      const uint32_t off = static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(OutT));
+      buf_store_q(ya, oa, off, static_cast<OutT*>(nullptr));
+      buf_store_q(yb, ob, off, static_cast<OutT*>(nullptr));
+    }
+  }
+}
+
+template <int LOGL, typename OutT, bool ADJ>
+int launch_fft(const GeoConst& gc, const RowBand& rb, double du, double dv, double sdd, double tau,
+               int kind, int64_t nrows, const float* e, OutT* q, hipStream_t st) {
+  using C = FftCfg<LOGL>;
+  const size_t lds = static_cast<size_t>(C::G) * C::BUF * sizeof(float2);
+  auto kern = &filter_fft_kernel<LOGL, OutT, ADJ>;
+  if (lds > 65536) {
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(lds));
+    if (err != hipSuccess) return static_cast<int>(err);
+  }
+  // Workgroups loop over row pairs (H is computed once per workgroup): a
+  // few per CU at most.
+  const int64_t npairs = (nrows + 1) / 2;
+  const int64_t want = (npairs + C::G - 1) / C::G;
+  const uint32_t groups = static_cast<uint32_t>(std::min<int64_t>(want, kFftMaxGroups));
+  hipLaunchKernelGGL(kern, dim3(groups), dim3(C::WG), lds, st, gc, rb, du, dv, sdd, tau, kind,
+                     nrows, e, q);
+  return static_cast<int>(hipGetLastError());
 }
 
 template <typename OutT, bool ADJ>
 int launch_filter_t(const GeoConst& gc, const RowBand& rb, double du, double dv, double sdd,
                     double tau, int kind, const float* e, void* q, hipStream_t st) {
   OutT* qt = static_cast<OutT*>(q);
-  const int64_t nrows = static_cast<int64_t>(rb.nviews) * rb.band;
   int32_t logl = 0;
   while ((1 << logl) < 2 * gc.nu - 1) ++logl;
-  if (gc.nu > kDirectMaxNu && logl <= kFftMaxLog) {
-    const int32_t L = 1 << logl;
-    const size_t lds = (static_cast<size_t>(L) + L / 2) * sizeof(float2);
-    const uint32_t groups = static_cast<uint32_t>((nrows + 2 * kFftRowPairs - 1) / (2 * kFftRowPairs));
-    if (lds > 65536) {
-      hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&filter_fft_kernel<OutT, ADJ>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           static_cast<int>(lds));
-      if (err != hipSuccess) return static_cast<int>(err);
+  // Launches of whole views and fewer than 2^30 rows (row indices and pair
+  // counts stay 32-bit inside the kernels).
+  const int32_t per = std::max<int32_t>(1, static_cast<int32_t>((int64_t{1} << 30) / rb.band));
+  for (int32_t s0 = 0; s0 < rb.nviews; s0 += per) {
+    RowBand sub = rb;
+    sub.nviews = std::min(per, rb.nviews - s0);
+    const float* es = e + s0 * rb.e_stride;
+    OutT* qs = qt + s0 * rb.q_stride;
+    const int64_t nrows = static_cast<int64_t>(sub.nviews) * sub.band;
+    if (nrows == 0) continue;
+    int err = 0;
+    if (gc.nu > kDirectMaxNu && logl <= kFftMaxLog) {
+      switch (logl) {
+        case 10: err = launch_fft<10, OutT, ADJ>(gc, sub, du, dv, sdd, tau, kind, nrows, es, qs, st); break;
+        case 11: err = launch_fft<11, OutT, ADJ>(gc, sub, du, dv, sdd, tau, kind, nrows, es, qs, st); break;
+        case 12: err = launch_fft<12, OutT, ADJ>(gc, sub, du, dv, sdd, tau, kind, nrows, es, qs, st); break;
+        default: err = launch_fft<13, OutT, ADJ>(gc, sub, du, dv, sdd, tau, kind, nrows, es, qs, st); break;
+      }
+    } else {
+      const size_t lds = 2 * static_cast<size_t>(gc.nu) * sizeof(float);
+      hipLaunchKernelGGL((filter_direct_kernel<OutT, ADJ>), dim3(static_cast<uint32_t>(nrows)),
+                         dim3(kFilterThreads), lds, st, gc, sub, du, dv, sdd, tau, kind, es, qs);
+      err = static_cast<int>(hipGetLastError());
     }
-    hipLaunchKernelGGL((filter_fft_kernel<OutT, ADJ>), dim3(groups), dim3(kFilterThreads), lds, st, gc,
-                       rb, du, dv, sdd, tau, kind, logl, nrows, e, qt);
-  } else {
-    const size_t lds = 2 * static_cast<size_t>(gc.nu) * sizeof(float);
-    hipLaunchKernelGGL((filter_direct_kernel<OutT, ADJ>), dim3(static_cast<uint32_t>(nrows)),
-                       dim3(kFilterThreads), lds, st, gc, rb, du, dv, sdd, tau, kind, e, qt);
+    if (err) return err;
   }
-  return static_cast<int>(hipGetLastError());
+  return 0;
 }
 
 }  // namespace
