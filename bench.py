@@ -107,6 +107,9 @@ def parse():
     ap.add_argument("--no-slab", action="store_true",
                     help="skip the streamed 4096^2-slab leg of the default run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="also time the oracle on whole volumes: 512^3 from 512 views (~2 min on "
+                         "16 threads) and one 256^3 volume from 360 views")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB (a plain copy of known size, "
                          "whose HBM counters scale the kernel's)")
@@ -334,6 +337,28 @@ def run_filter(dev):
     return out
 
 
+def oracle_configs(oracle, threads):
+    """Whole-volume oracle back-projections of the smaller workloads (FP64,
+    all threads): 512^3 from 512 views of 512^2 and one 256^3 volume from 360
+    views of 384^2."""
+    import numpy as np
+
+    import synth
+    out = {}
+    for name in ("bp512", "diff256"):
+        c = synth.config(name)
+        g, ang = c["geom"], synth.angles(c["np"])
+        q = np.random.default_rng(7).standard_normal((c["np"], g.nv, g.nu))
+        t = time.time()
+        oracle.backproject(g, ang, q)
+        el = time.time() - t
+        ups = float(g.nx) * g.ny * g.nz * c["np"]
+        out[f"{name}_full_volume_s"] = round(el, 2)
+        out[f"{name}_gups"] = round(gups(ups, el), 5)
+        log(f"cpu oracle {name}: whole volume in {el:.1f} s ({gups(ups, el):.4f} GUPS, {threads} threads)")
+    return out
+
+
 def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic):
     per_launch_s = ms_step / 1e3 / launches
     updates_per_launch = updates / launches
@@ -439,6 +464,8 @@ def main():
     scale = fdk.fdk_scale(g, ang)
     vol = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=dev)
 
+    step_ms = {}
+
     def timed_bp(q, steps, warmup, label):
         for _ in range(warmup):
             fdk.backproject(q, g, ang, out=vol, scale=scale)
@@ -454,6 +481,7 @@ def main():
         wall = time.time() - wall0
         ms = [starts[k].elapsed_time(ends[k]) for k in range(steps)]
         log(f"{label}: step ms {['%.1f' % m for m in ms]} (wall {wall:.2f} s)")
+        step_ms[label] = ms
         return sum(ms) / len(ms)
 
     # ---- FP32 storage: the headline figure ----
@@ -511,6 +539,12 @@ def main():
         result_extra["slab4096_bp_ms"] = round(bp_ms, 1)
         result_extra["slab4096_pipeline_ms"] = round(wall_ms, 1)
 
+    # ---- the other legs against the same kernel's roofs ----
+    valu_roof = roofline["valu_roof_gups"]
+    for key in ("f16_store_gups", "bf16_store_gups", "bp512_gups", "slab4096_f16_gups"):
+        if key in result_extra:
+            result_extra[key.replace("_gups", "_valu_frac")] = round(result_extra[key] / valu_roof, 4)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the workload ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -538,6 +572,13 @@ def main():
         oracle.set_num_threads(threads)
         model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo")
                       if ln.startswith("model name")), "unknown")
+        # the 64^3 FDK's whole volume (64 views), all threads
+        c1 = synth.config("fdk64")
+        g1, a1 = c1["geom"], synth.angles(c1["np"])
+        q1 = rng.standard_normal((c1["np"], g1.nv, g1.nu))
+        t1 = time.time()
+        oracle.backproject(g1, a1, q1)
+        el_c1 = time.time() - t1
         rate = gups(done, el)
         cpu = {"value": round(rate, 5), "unit": "GUPS", "cores": threads, "kind": "oracle",
                "sample": f"{done} voxel-view updates ({nvox} random voxels of the "
@@ -545,13 +586,17 @@ def main():
                          f"repeated for {el:.1f} s)",
                "single_thread_gups": round(gups(done1, el1), 5),
                "cpu_model": model, "host_cpus": os.cpu_count(),
-               "extrapolated_full_step_s": round(updates / (rate * 2 ** 30), 0)}
+               "extrapolated_full_step_s": round(updates / (rate * 2 ** 30), 0),
+               "fdk64_full_volume_s": round(el_c1, 4)}
+        if args.oracle_configs:
+            cpu.update(oracle_configs(oracle, threads))
         log(f"cpu oracle: {cpu['value']} GUPS on {threads} threads, {cpu['single_thread_gups']} on one "
             f"({model}); a full step would take ~{cpu['extrapolated_full_step_s']:.0f} s")
 
     out = {
         "metric": METRIC, "value": round(gups32, 2), "unit": "GUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms32, 2),
+        "ms_per_step_median": round(float(np.median(step_ms["fp32"])), 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: seeded 32-ellipsoid phantom, analytic line integrals, "
                 "Shepp-Logan filtered on the GPU",
