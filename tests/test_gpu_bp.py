@@ -311,12 +311,14 @@ def test_bp_edge_geometries(name):
     assert rel_l2(fp, fref) <= 1e-5
 
 
-@pytest.mark.parametrize("nu", [1000, 2048, 4096])
+@pytest.mark.parametrize("nu", [257, 300, 512, 513, 1000, 2048, 4096])
 @pytest.mark.parametrize("kind", ["ramlak", "shepp-logan"])
 def test_filter_fft_path_matches_oracle(nu, kind):
-    """Rows above 256 pixels take the FFT path (2048: 4096-point FFTs,
-    4096: 8192-point FFTs in 96 KB of LDS); an odd row count exercises the
-    unpaired last row."""
+    """Rows above 256 pixels take the FFT path: 257-512 pixels 1024-point
+    FFTs (four per workgroup, a radix-4 first pass), up to 1024 2048-point
+    (radix-8 first pass), up to 2048 4096-point (radix 16 only), up to 4096
+    8192-point (radix-2 first pass, 512-thread workgroups); an odd row count
+    exercises the unpaired last row."""
     g = BASE.replace(nu=nu, nv=3, off_u=0.25, sod=4.0 * nu, sdd=8.0 * nu)
     ang = synth.angles(3)
     e = np.random.default_rng(nu).uniform(0, 50, (3, g.nv, g.nu)).astype(np.float32)
