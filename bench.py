@@ -414,9 +414,9 @@ def main_slab(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(one GPU's share is the workload; see the design notes on sharding).",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path. The workload is "
+              "one GPU's share; mirror-pair slabs of the volume shard across GPUs with no "
+              "reduction, each GPU receiving every filtered view.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "slab4096":

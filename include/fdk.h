@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
   FDK_OK = 0,
   FDK_ERR_INVALID_ARG = 1, /* a pointer, size, range or geometry is invalid */
-  FDK_ERR_UNSUPPORTED = 2, /* a dtype, filter or slab kind this build lacks */
+  FDK_ERR_UNSUPPORTED = 2, /* a dtype, filter or slab kind the library does not support */
   FDK_ERR_HIP = 3,         /* the HIP runtime reported an error */
   FDK_ERR_OUT_OF_MEMORY = 4
 } fdk_status;
