@@ -264,6 +264,18 @@ def run_configs(dev):
     ms = timed(fdk64, 20)
     out["fdk64_ms"] = round(ms, 4)
     out["fdk64_gups"] = round(gups(float(g.nx) * g.ny * g.nz * c["np"], ms / 1e3), 2)
+    # the same two launches replayed from a HIP graph (launch overhead removed)
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        fdk64()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fdk64()
+    out["fdk64_graph_ms"] = round(timed(graph.replay, 50), 4)
+    del graph
     # 512^3 back-projection from 512 views of 512^2
     c = synth.config("bp512")
     g, ang = c["geom"], synth.angles(c["np"])
@@ -290,7 +302,8 @@ def run_configs(dev):
         (fdk.fdk_backprojection(qb, g, ang, scale) * w).sum().backward()
     ms = timed(step, 3)
     out["diff256_step_ms"] = round(ms, 2)
-    log(f"configs: fdk64 {out['fdk64_ms']} ms ({out['fdk64_gups']} GUPS), bp512 {out['bp512_ms']} ms "
+    log(f"configs: fdk64 {out['fdk64_ms']} ms ({out['fdk64_gups']} GUPS; {out['fdk64_graph_ms']} ms "
+        f"replayed from a graph), bp512 {out['bp512_ms']} ms "
         f"({out['bp512_gups']} GUPS), diff256 forward+backward {out['diff256_step_ms']} ms")
     return out
 

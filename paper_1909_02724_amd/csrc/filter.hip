@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "geom_device.h"
 #include "ops_internal.h"
@@ -454,10 +455,19 @@ int launch_fft(const GeoConst& gc, const RowBand& rb, double du, double dv, doub
   const size_t lds = static_cast<size_t>(C::G) * C::BUF * sizeof(float2);
   auto kern = &filter_fft_kernel<LOGL, OutT, ADJ>;
   if (lds > 65536) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(lds));
+    // Raised once per device and kernel, so launches recorded into a graph
+    // after the first (eager) call make no attribute call.
+    static std::atomic<uint64_t> raised{0};
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
     if (err != hipSuccess) return static_cast<int>(err);
+    const uint64_t bit = uint64_t{1} << (dev & 63);
+    if (!(raised.load(std::memory_order_acquire) & bit)) {
+      err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+      if (err != hipSuccess) return static_cast<int>(err);
+      raised.fetch_or(bit, std::memory_order_release);
+    }
   }
   // Workgroups loop over row pairs (H is computed once per workgroup): a
   // few per CU at most.
