@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "brick.h"
 
@@ -80,6 +81,7 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
 // is then about 2^-31 of K M: the error is far below that of the FP32 sum
 // for the real overlap of a brick's footprint.
 constexpr int32_t kHistStride = kThreads;  // tile columns tu + 1 <= 256
+constexpr int64_t kFpSplitTarget = 4096;    // workgroups below which views are split
 
 template <bool MIRROR>
 __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRun run,
@@ -93,9 +95,17 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
   __shared__ uint32_t amax_bits;
   const int32_t tid = threadIdx.x;
+  // blockIdx.y picks this workgroup's share of the launch's views: small
+  // volumes split the views over several workgroups per brick (the
+  // projections take their sums through atomics either way), so the grid
+  // fills the chip more than once over.
+  const int32_t per = (vb.nviews + static_cast<int32_t>(gridDim.y) - 1) / static_cast<int32_t>(gridDim.y);
+  const int32_t v_lo = static_cast<int32_t>(blockIdx.y) * per;
+  const int32_t v_hi = min(vb.nviews, v_lo + per);
+  if (v_lo >= v_hi) return;  // uniform, before any barrier
   const BrickCoords bc = brick_coords(gc, run, ts);
   if (tid == 0) amax_bits = 0u;
-  if (tid < vb.nviews)
+  if (tid >= v_lo && tid < v_hi)
     bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
   const uint32_t rot = slot_rotation();
   float x[kBrickZ], xm[kBrickZ];
@@ -113,8 +123,8 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   const int32_t slot = tuf * tvp;
   const int32_t rstep = kThreads / tuf;
   const int32_t sr = tid / tuf, sc = tid - sr * tuf;
-  for (int32_t s0 = 0; s0 < vb.nviews; s0 += ts.vc) {
-    const int32_t nvc = min(ts.vc, vb.nviews - s0);
+  for (int32_t s0 = v_lo; s0 < v_hi; s0 += ts.vc) {
+    const int32_t nvc = min(ts.vc, v_hi - s0);
     // Main rows in planes [0, vc) and mirror rows in planes [vc, 2 vc), one
     // 32-bit word per pixel: all LDS banks serve the adds (interleaved
     // (main, mirror) pairs reached only half of them and conflicted 10-way).
@@ -260,9 +270,17 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
                            const TileShape& ts, const float* vol, float* q, int64_t vstride,
                            float scale, void* stream) {
   const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
-  const dim3 grid(static_cast<uint32_t>(nwg)), block(kThreads);
+  const dim3 block(kThreads);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ts.vc > 0) {
+    // Views split over workgroups when the bricks alone give fewer than
+    // kFpSplitTarget workgroups (FDK_FP_VSPLIT=n overrides: a tuning aid).
+    int64_t vsplit = 1;
+    if (nwg < static_cast<uint64_t>(kFpSplitTarget))
+      vsplit = (kFpSplitTarget + static_cast<int64_t>(nwg) - 1) / static_cast<int64_t>(nwg);
+    if (const char* env = std::getenv("FDK_FP_VSPLIT")) vsplit = std::atoi(env);
+    vsplit = std::max<int64_t>(1, std::min<int64_t>(vsplit, vb.nviews));
+    const dim3 grid(static_cast<uint32_t>(nwg), static_cast<uint32_t>(vsplit));
     // Adjoint tile: one more column than the back-projection tile, float2
     // entries; it always fits where the back-projection tile does.
     TileShape tf = ts;
@@ -276,6 +294,7 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
       hipLaunchKernelGGL((fp_tiled_kernel<false>), grid, block, lds, st, gc, run, vb, tf, vol,
                          q, vstride, scale);
   } else {
+    const dim3 grid(static_cast<uint32_t>(nwg));
     if (run.mirror)
       hipLaunchKernelGGL((fp_direct_kernel<true>), grid, block, 0, st, gc, run, vb, ts, vol, q,
                          vstride, scale);
