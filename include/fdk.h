@@ -214,6 +214,16 @@ FDK_API fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int3
                                       float lambda, uint32_t flags, float* proj_tmp,
                                       float* vol_tmp, void* stream);
 
+/* The 3 x 4 projection matrix P_s of Eq. 2 that every kernel uses for view
+ * `view` (angle g->angles[view]), in the reduced form of Eq. 3 and
+ * Theorems 2-3: for voxel (i, j, k), [x, y, z] = P [i, j, k, 1] with z the
+ * depth along the central ray (the geometry's length unit) and
+ * (u, v) = (x / z, y / z) in detector pixels. P: host array of 12 doubles,
+ * row-major, owned by the caller. Host-only: validates g and view like the
+ * other calls and makes no HIP call. Errors: FDK_ERR_INVALID_ARG for an
+ * invalid geometry, a view outside [0, np) or a null P. */
+FDK_API fdk_status fdk_projection_matrix(const fdk_geometry* g, int32_t view, double* P);
+
 /* pi * d^2 / Np: the FDK constant (1/2) * (2 pi / Np) * d^2 of a full
  * 360-degree scan, since W = 1/z^2 carries no d^2. Returns NaN for a null
  * or invalid geometry. */

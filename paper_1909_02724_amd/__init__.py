@@ -118,6 +118,8 @@ def lib():
         L.fdk_slab_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int, C.POINTER(C.c_int32)]
         L.fdk_fdk_scale.restype = C.c_double
         L.fdk_fdk_scale.argtypes = [P]
+        L.fdk_projection_matrix.restype = C.c_int
+        L.fdk_projection_matrix.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
         L.fdk_last_error.restype = C.c_char_p
         L.fdk_last_error.argtypes = []
         _lib = L
@@ -260,6 +262,15 @@ def filter_adjoint(gq: torch.Tensor, geom, angles, *, view0: int = 0, kind: str 
     _check(lib().fdk_filter_adjoint(C.byref(cg), view0, gq.shape[0], C.c_void_p(gq.data_ptr()),
                                     C.c_void_p(out.data_ptr()), _FILTERS[kind], _stream(gq)))
     return out
+
+
+def projection_matrix(geom, angles, view: int) -> np.ndarray:
+    """The (3, 4) matrix P of Eq. 2 the kernels use for view `view`:
+    [x, y, z] = P [i, j, k, 1], (u, v) = (x / z, y / z) in pixels."""
+    cg, _keep = _cgeom(geom, angles)
+    out = (C.c_double * 12)()
+    _check(lib().fdk_projection_matrix(C.byref(cg), int(view), out))
+    return np.array(out[:], dtype=np.float64).reshape(3, 4)
 
 
 def fdk_scale(geom, angles) -> float:

@@ -190,6 +190,26 @@ extern "C" {
 
 const char* fdk_last_error(void) { return g_last_error.c_str(); }
 
+fdk_status fdk_projection_matrix(const fdk_geometry* g, int32_t view, double* P) {
+  fdk_status st = check_geometry(g);
+  if (st != FDK_OK) return st;
+  if ((st = check_views(g, view, 1)) != FDK_OK) return st;
+  if (!P) return fail(FDK_ERR_INVALID_ARG, "matrix pointer is NULL");
+  // The kernels' own constants: z = ci i + cj j + c0, u = cu + ku a / z,
+  // v = cv + kv (k - cz) / z, a = ai i + aj j + a0.
+  const fdk::GeoConst gc = make_geo(g);
+  const fdk::ViewGeo vg = make_view(g, g->angles[view]);
+  const double zr[4] = {vg.ci, vg.cj, 0.0, vg.c0};
+  const double ar[4] = {vg.ai, vg.aj, 0.0, vg.a0};
+  const double kr[4] = {0.0, 0.0, 1.0, -gc.cz};
+  for (int c = 0; c < 4; ++c) {
+    P[c] = gc.cu * zr[c] + gc.ku * ar[c];
+    P[4 + c] = gc.cv * zr[c] + gc.kv * kr[c];
+    P[8 + c] = zr[c];
+  }
+  return ok();
+}
+
 double fdk_fdk_scale(const fdk_geometry* g) {
   if (!g || g->np <= 0 || !std::isfinite(g->sod)) return std::nan("");
   return M_PI * g->sod * g->sod / g->np;

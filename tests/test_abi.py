@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import paper_1909_02724_amd as fdk
+import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "fdk.h")
@@ -221,3 +222,37 @@ def test_sirt_validation():
     assert it(C.byref(cg), 0, 4, A, B_, C_, D_, 0, 8, 0, float("nan"), 0, E_, F_, None) == 1
     assert it(C.byref(cg), 0, 4, A, B_, C_, D_, 0, 8, 0, 1.0, 8, E_, F_, None) == 1
     assert "flags" in L.fdk_last_error().decode()
+
+
+@pytest.mark.parametrize("gi", [0, 1, 2])
+def test_projection_matrix_matches_oracle(orc, gi):
+    """The host geometry the kernels are built from (fdk_projection_matrix,
+    no HIP call) equals the oracle's literal product M1 Mrot(b) M0 (Eq. 2)
+    for offset principal points, anisotropic pitches and any angle."""
+    geoms = [
+        synth.Geom(nx=12, ny=10, nz=8, nu=20, nv=14, sod=60.0, sdd=110.0,
+                   dx=1.0, dy=1.3, dz=0.8, du=1.7, dv=1.1),
+        synth.Geom(nx=9, ny=9, nz=7, nu=16, nv=11, sod=45.0, sdd=80.0,
+                   dx=0.9, dy=0.9, dz=1.2, du=2.0, dv=2.0, off_u=0.75, off_v=-1.25),
+        synth.config("bp2048")["geom"],
+    ]
+    g = geoms[gi]
+    ang = np.array([0.0, 0.3, 1.1, np.pi / 2, 2.5, np.pi, 4.0, 5.9, -7.3])
+    for s, beta in enumerate(ang):
+        got = fdk.projection_matrix(g, ang, s)
+        ref = orc.projection_matrix(g, beta)
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_projection_matrix_validation():
+    g = synth.Geom(nx=8, ny=8, nz=8, nu=12, nv=12, sod=40.0, sdd=80.0)
+    ang = np.array([0.0, 1.0])
+    with pytest.raises(fdk.FDKError):
+        fdk.projection_matrix(g, ang, 2)
+    with pytest.raises(fdk.FDKError):
+        fdk.projection_matrix(g, ang, -1)
+    with pytest.raises(fdk.FDKError):
+        fdk.projection_matrix(g, np.array([0.0, np.nan]), 1)
+    L = fdk.lib()
+    cg, _keep = fdk._cgeom(g, ang)
+    assert L.fdk_projection_matrix(C.byref(cg), 0, None) == fdk.FDK_ERR_INVALID_ARG
