@@ -108,6 +108,39 @@ def test_bp2048_full_size_sampled():
         assert e_f32 <= 2e-3
 
 
+def test_adjoint_2048_dot_full_size():
+    """The adjoint in the benchmark's adjoint configuration (2048^3, 256
+    views of 2048^2, 32 views per launch): <B q, x> = <q, F x> on positive
+    data to 1e-6 relative, inner products in FP64 slab by slab. B is pinned
+    to the oracle at this size by test_bp2048_full_size_sampled, so this
+    checks F there as its transpose."""
+    import synth.gpu as sg
+    c = synth.config("bp2048")
+    g = c["geom"]
+    ang = synth.angles(c["np"])
+    nviews = 256
+    announce("adjoint 2048: filling 4 GiB of projections and a 32 GiB volume")
+    q = sg.hash_fill(torch.empty((nviews, g.nv, g.nu), dtype=torch.float32, device=DEV), 4096)
+    q.add_(1.5)
+    x = sg.hash_fill(torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=DEV), 4097)
+    x.add_(1.5)
+    announce("adjoint 2048: back-projection of 256 views")
+    bq = fdk.backproject(q, g, ang)
+    lhs = 0.0
+    for k0 in range(0, g.nz, 64):
+        lhs += float((bq[k0:k0 + 64].double() * x[k0:k0 + 64].double()).sum())
+    del bq
+    torch.cuda.empty_cache()
+    announce("adjoint 2048: forward projection of 256 views")
+    fx = fdk.forward_project(x, g, ang, nviews=nviews)
+    rhs = 0.0
+    for s0 in range(0, nviews, 32):
+        rhs += float((q[s0:s0 + 32].double() * fx[s0:s0 + 32].double()).sum())
+    announce(f"adjoint 2048: <Bq, x> {lhs:.12e}, <q, Fx> {rhs:.12e}, "
+             f"relative difference {abs(lhs - rhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
+
+
 def test_diff256_autograd_checks():
     """Differentiable workload: a batch of 4 volumes of 256^3 back-projected
     from 360 views of 384^2; backward is the matched forward projector.
