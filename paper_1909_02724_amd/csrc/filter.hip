@@ -23,6 +23,12 @@
 #include "geom_device.h"
 #include "ops_internal.h"
 
+// Multiply-adds fuse only within one expression (the explicit fmaf calls
+// and single-expression products), never across statements after
+// inlining: the arithmetic is then the same in every instantiation, so the
+// 16-bit outputs are exactly the FP32 output rounded.
+#pragma clang fp contract(on)
+
 namespace fdk {
 namespace {
 

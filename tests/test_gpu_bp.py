@@ -105,6 +105,20 @@ def test_filter_matches_oracle(kind, dtype):
     assert rel_l2(got, ref) <= tol
 
 
+@pytest.mark.parametrize("nu", [100, 1000, 4096])
+def test_filter_16bit_store_is_rounded_fp32(nu):
+    """The filter computes in FP32 whatever it stores: FP16 and BF16 outputs
+    are the FP32 output rounded to nearest even, bit for bit (direct path,
+    2048- and 8192-point FFTs)."""
+    g = BASE.replace(nu=nu, nv=5, off_u=0.3, sod=4.0 * nu, sdd=8.0 * nu)
+    ang = synth.angles(3)
+    e = gpu(np.random.default_rng(nu + 7).uniform(0, 30, (3, g.nv, g.nu)).astype(np.float32))
+    q32 = fdk.filter(e, g, ang, kind="shepp-logan")
+    for dt in (torch.float16, torch.bfloat16):
+        q16 = fdk.filter(e, g, ang, kind="shepp-logan", dtype=dt)
+        assert torch.equal(q16, q32.to(dt)), dt
+
+
 SLABS = [
     ("contiguous", 0, 38),    # whole volume
     ("contiguous", 5, 20),    # [5, 25): paired 13..24 with 13..24? mixed paired/plain
