@@ -106,6 +106,9 @@ def parse():
                     help="skip the filtering leg (2048- and 4096-pixel rows) of the default run")
     ap.add_argument("--no-slab", action="store_true",
                     help="skip the streamed 4096^2-slab leg of the default run")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also time the back-projector without mirror pairs and without LDS "
+                         "staging (2048^3, 64 views)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--oracle-configs", action="store_true",
                     help="also time the oracle on whole volumes: 512^3 from 512 views (~2 min on "
@@ -350,6 +353,53 @@ def run_filter(dev):
     return out
 
 
+def run_ablation(dev):
+    """What each part of the kernel's design contributes, on the 2048^3
+    geometry with 64 views of FP32 projections: the tiled kernel with
+    mirror pairs (Theorem 1), the same without mirror pairs (a fractional
+    principal-point offset leaves no pixel-aligned mirror, so every slice is
+    back-projected on its own), and the direct variant (taps read from
+    global memory, no LDS staging; FDK_BP_KERNEL=direct)."""
+    import torch
+
+    import paper_1909_02724_amd as fdk
+    import synth
+    import synth.gpu as sg
+
+    c = synth.config("bp2048")
+    g0, ang = c["geom"], synth.angles(c["np"])
+    n = 64
+    q = sg.hash_fill(torch.empty((n, g0.nv, g0.nu), dtype=torch.float32, device=dev), 5)
+    vol = torch.empty((g0.nz, g0.ny, g0.nx), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    prev = os.environ.pop("FDK_BP_KERNEL", None)
+    try:
+        for key, g, env in (("ablation_tiled_mirror_gups", g0, None),
+                            ("ablation_tiled_no_mirror_gups", g0.replace(off_v=0.27), None),
+                            ("ablation_direct_mirror_gups", g0, "direct")):
+            if env:
+                os.environ["FDK_BP_KERNEL"] = env
+            else:
+                os.environ.pop("FDK_BP_KERNEL", None)
+            fdk.backproject(q[:32], g, ang, out=vol)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fdk.backproject(q, g, ang, out=vol)
+            b.record(stream)
+            torch.cuda.synchronize()
+            out[key] = round(gups(float(g.nx) * g.ny * g.nz * n, a.elapsed_time(b) / 1e3), 1)
+            log(f"ablation: {key} = {out[key]}")
+    finally:
+        os.environ.pop("FDK_BP_KERNEL", None)
+        if prev is not None:
+            os.environ["FDK_BP_KERNEL"] = prev
+    del q, vol
+    torch.cuda.empty_cache()
+    return out
+
+
 def oracle_configs(oracle, threads):
     """Whole-volume oracle back-projections of the smaller workloads (FP64,
     all threads): 512^3 from 512 views of 512^2 and one 256^3 volume from 360
@@ -541,6 +591,9 @@ def main():
 
     if not args.no_filter and args.workload == "bp2048":
         result_extra.update(run_filter(dev))
+
+    if args.ablation and args.workload == "bp2048":
+        result_extra.update(run_ablation(dev))
 
     if not args.no_slab and args.workload == "bp2048":
         del q32
