@@ -87,17 +87,25 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   const bool owner = (i_lo + tx0 <= i_hi) && (j_lo + ty0 <= j_hi);
   const int32_t i = min(i_lo + tx0, i_hi), j = min(j_lo + ty0, j_hi);
   const float txf = static_cast<float>(i - i_lo), tyf = static_cast<float>(j - j_lo);
-  const int32_t t0 = seg * kBrickZ;
+  // Mirrored runs: 16 slices and their mirrors per thread, tile entries
+  // (q, dq, qm, dqm). Plain runs: 32 slices per thread (the second 16 in the
+  // registers the mirrors would use), entries (q, dq).
+  constexpr int BZ = MIRROR ? kBrickZ : kPlainBrickZ;
+  constexpr uint32_t kEntry = MIRROR ? kTileEntryBytes : kPlainEntryBytes;
+  const int32_t t0 = seg * BZ;
   const int32_t kb = run.k_first + t0;
   const float kvf = static_cast<float>(gc.kv);
 
   if (tid < vb.nviews)
-    bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb, ts.tu, ts.tv);
+    bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb, ts.tu, ts.tv, BZ, MIRROR);
   __syncthreads();
 
   float acc[kBrickZ], accm[kBrickZ];
 #pragma unroll
   for (int t = 0; t < kBrickZ; ++t) acc[t] = accm[t] = 0.0f;
+  // Accumulator of slice t (plain runs: t < 32); t is a constant after
+  // unrolling, so this selects a register.
+  auto slice_acc = [&](int t) -> float& { return t < kBrickZ ? acc[t] : accm[t - kBrickZ]; };
 
   if constexpr (TILED) {
     const int32_t tu = ts.tu, tv = ts.tv, tvp = ts.tvp, rstep = ts.rstep, rows = ts.rows;
@@ -109,7 +117,9 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     const uint32_t es = sizeof(T);
     const uint32_t row_es = static_cast<uint32_t>(gc.nu) * es;
     const uint32_t nrec = static_cast<uint32_t>(gc.nu) * static_cast<uint32_t>(gc.nv) * es;
-    uint4 pre[kPrefetchSlots];  // raw bits of (q(u), q(u+1)) for the row and its mirror
+    // Raw bits of (q(u), q(u+1)) for the row and (mirrored runs) its mirror.
+    constexpr int NSLOT = MIRROR ? kPrefetchSlots : kPlainPrefetchSlots;
+    uint4 pre[NSLOT];
 
     // Issue the loads of views [s0, s0 + nvc) into pre[]: raw (q(u), q(u+1))
     // for the row and for its mirror row. Views whose tile lies on the
@@ -120,7 +130,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
       uint32_t c0 = 0, c1 = 0, off = 0, offm = 0;
       const uint32_t step = static_cast<uint32_t>(rstep) * row_es;
 #pragma unroll
-      for (int m = 0; m < kPrefetchSlots; ++m) {
+      for (int m = 0; m < NSLOT; ++m) {
         if (sl < nvc) {
           // The descriptor is rebuilt per slot (scalar work): carried across
           // slots, the compiler moves it to vector registers and wraps each
@@ -186,13 +196,18 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     auto store_stage = [&](int32_t nvc) {
       int32_t sl = 0, rr = 0;
 #pragma unroll
-      for (int m = 0; m < kPrefetchSlots; ++m) {
+      for (int m = 0; m < NSLOT; ++m) {
         if (sl < nvc) {
           const int32_t r = sr + rr * rstep;
           if (stager && r < tv) {
             const float a0 = raw_to_f32<T>(pre[m].x), a1 = raw_to_f32<T>(pre[m].y);
-            const float b0 = raw_to_f32<T>(pre[m].z), b1 = raw_to_f32<T>(pre[m].w);
-            tile[sl * slot_entries + sc * tvp + r] = make_float4(a0, a1 - a0, b0, b1 - b0);
+            if constexpr (MIRROR) {
+              const float b0 = raw_to_f32<T>(pre[m].z), b1 = raw_to_f32<T>(pre[m].w);
+              tile[sl * slot_entries + sc * tvp + r] = make_float4(a0, a1 - a0, b0, b1 - b0);
+            } else {
+              reinterpret_cast<float2*>(tile)[sl * slot_entries + sc * tvp + r] =
+                  make_float2(a0, a1 - a0);
+            }
           }
         }
         if (++rr == rows) {
@@ -216,7 +231,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
         // One register holds the column's tile offset, so each pair's
         // address is a single shift-and-add.
         uint32_t cbase = (static_cast<uint32_t>(sl * slot_entries) +
-                          nu * static_cast<uint32_t>(tvp) + c.nvb) * kTileEntryBytes;
+                          nu * static_cast<uint32_t>(tvp) + c.nvb) * kEntry;
         asm volatile("" : "+v"(cbase));
         const char* pb = tile_bytes + cbase;
         // Reads run one voxel pair ahead of use, so LDS latency overlaps the
@@ -224,28 +239,49 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
         uint32_t dn;
         float fr;
         voxel_row_off(c.fvb, c.dvk, 0, &dn, &fr);
-        float4 A = reinterpret_cast<const float4*>(pb + dn * kTileEntryBytes)[0];
-        float4 B = reinterpret_cast<const float4*>(pb + dn * kTileEntryBytes)[1];
+        if constexpr (MIRROR) {
+          float4 A = reinterpret_cast<const float4*>(pb + dn * kEntry)[0];
+          float4 B = reinterpret_cast<const float4*>(pb + dn * kEntry)[1];
 #pragma unroll
-        for (int t = 0; t < kBrickZ; ++t) {
-          float4 An = A, Bn = B;
-          uint32_t dn1 = 0;
-          float fr1 = 0.0f;
-          if (t + 1 < kBrickZ) {
-            voxel_row_off(c.fvb, c.dvk, t + 1, &dn1, &fr1);
-            const float4* p = reinterpret_cast<const float4*>(pb + dn1 * kTileEntryBytes);
-            An = p[0];
-            Bn = p[1];
-          }
-          const float ta = fmaf(c.du, A.y, A.x), tb = fmaf(c.du, B.y, B.x);
-          acc[t] = fmaf(c.w, fmaf(fr, tb - ta, ta), acc[t]);
-          if (MIRROR) {
+          for (int t = 0; t < kBrickZ; ++t) {
+            float4 An = A, Bn = B;
+            uint32_t dn1 = 0;
+            float fr1 = 0.0f;
+            if (t + 1 < kBrickZ) {
+              voxel_row_off(c.fvb, c.dvk, t + 1, &dn1, &fr1);
+              const float4* p = reinterpret_cast<const float4*>(pb + dn1 * kEntry);
+              An = p[0];
+              Bn = p[1];
+            }
+            const float ta = fmaf(c.du, A.y, A.x), tb = fmaf(c.du, B.y, B.x);
+            acc[t] = fmaf(c.w, fmaf(fr, tb - ta, ta), acc[t]);
             const float ma = fmaf(c.du, A.w, A.z), mb = fmaf(c.du, B.w, B.z);
             accm[t] = fmaf(c.w, fmaf(fr, mb - ma, ma), accm[t]);
+            A = An;
+            B = Bn;
+            fr = fr1;
           }
-          A = An;
-          B = Bn;
-          fr = fr1;
+        } else {
+          // Rows n and n + 1 are adjacent 8-byte entries: one read2.
+          float2 A = reinterpret_cast<const float2*>(pb + dn * kEntry)[0];
+          float2 B = reinterpret_cast<const float2*>(pb + dn * kEntry)[1];
+#pragma unroll
+          for (int t = 0; t < BZ; ++t) {
+            float2 An = A, Bn = B;
+            uint32_t dn1 = 0;
+            float fr1 = 0.0f;
+            if (t + 1 < BZ) {
+              voxel_row_off(c.fvb, c.dvk, t + 1, &dn1, &fr1);
+              const float2* p = reinterpret_cast<const float2*>(pb + dn1 * kEntry);
+              An = p[0];
+              Bn = p[1];
+            }
+            const float ta = fmaf(c.du, A.y, A.x), tb = fmaf(c.du, B.y, B.x);
+            slice_acc(t) = fmaf(c.w, fmaf(fr, tb - ta, ta), slice_acc(t));
+            A = An;
+            B = Bn;
+            fr = fr1;
+          }
         }
       }
     }
@@ -256,7 +292,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
       const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
       const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);
 #pragma unroll
-      for (int t = 0; t < kBrickZ; ++t) {
+      for (int t = 0; t < BZ; ++t) {
         uint32_t dn;
         float fr;
         voxel_row_off(c.fvb, c.dvk, t, &dn, &fr);
@@ -264,7 +300,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
         const float q0a = tap(qs, gc.nu, gc.nv, a, n), q1a = tap(qs, gc.nu, gc.nv, a + 1, n);
         const float q0b = tap(qs, gc.nu, gc.nv, a, n + 1), q1b = tap(qs, gc.nu, gc.nv, a + 1, n + 1);
         const float ta = fmaf(c.du, q1a - q0a, q0a), tb = fmaf(c.du, q1b - q0b, q0b);
-        acc[t] = fmaf(c.w, fmaf(fr, tb - ta, ta), acc[t]);
+        slice_acc(t) = fmaf(c.w, fmaf(fr, tb - ta, ta), slice_acc(t));
         if (MIRROR) {
           // Theorem 1: v(Nz-1-k) = G - v(k): rows G - n (weight 1 - fr) and
           // G - n - 1 (weight fr).
@@ -282,10 +318,10 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   const int64_t slice = static_cast<int64_t>(gc.nx) * gc.ny;
   const int64_t col = static_cast<int64_t>(j) * gc.nx + i;
 #pragma unroll
-  for (int t = 0; t < kBrickZ; ++t) {
+  for (int t = 0; t < BZ; ++t) {
     if (t0 + t >= run.n) break;
     float* p = vol + static_cast<int64_t>(run.loc_lo + t0 + t) * slice + col;
-    *p = accumulate ? fmaf(scale, acc[t], *p) : scale * acc[t];
+    *p = accumulate ? fmaf(scale, slice_acc(t), *p) : scale * slice_acc(t);
     if (MIRROR) {
       float* pm = vol + static_cast<int64_t>(run.loc_hi - t0 - t) * slice + col;
       *pm = accumulate ? fmaf(scale, accm[t], *pm) : scale * accm[t];
@@ -305,8 +341,9 @@ void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape t
   bp_brick_body<T, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
 }
 
+// The plain tiled variant is held to the same four waves per SIMD.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void bp_tiled_plain_kernel(GeoConst gc, SliceRun run,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void bp_tiled_plain_kernel(GeoConst gc, SliceRun run,
                                                                   ViewBatch vb, TileShape ts,
                                                                   const T* __restrict__ q,
                                                                   int64_t vstride,
@@ -337,7 +374,8 @@ int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, co
   const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
   const dim3 grid(static_cast<uint32_t>(nwg)), block(kThreads);
   if (ts.vc > 0) {
-    const size_t lds = static_cast<size_t>(ts.vc) * ts.tu * ts.tvp * kTileEntryBytes;
+    const size_t lds = static_cast<size_t>(ts.vc) * ts.tu * ts.tvp *
+                       (run.mirror ? kTileEntryBytes : kPlainEntryBytes);
     if (run.mirror)
       hipLaunchKernelGGL((bp_tiled_mirror_kernel<T>), grid, block, lds, st, gc, run, vb, ts,
                          qt, vstride, vol, scale, accumulate);
@@ -362,19 +400,19 @@ int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, co
 // half-diagonal and zmin = d - r,
 //   |du/di| <= ku Dx (|cos| + |sin| r / zmin) / zmin,
 //   |du/dj| <= ku Dy (|sin| + |cos| r / zmin) / zmin,
-// and v(k) - cv = kv (k - cz) / z, so over 16 slices and the brick's z
-// spread dz the rows span at most kv ((16 - 1) / zmin + |k - cz| dz / zmin^2).
+// and v(k) - cv = kv (k - cz) / z, so over the brick's bz slices and its z
+// spread dz the rows span at most kv ((bz - 1) / zmin + |k - cz| dz / zmin^2).
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
-                     const ViewBatch& vb) {
+                     const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots) {
   TileShape ts{};
   ts.nbx = (gc.nx + kBrickX - 1) / kBrickX;
   ts.nby = (gc.ny + kBrickY - 1) / kBrickY;
-  ts.nseg = (run.n + kBrickZ - 1) / kBrickZ;
+  ts.nseg = (run.n + bz - 1) / bz;
   const double r = 0.5 * std::hypot((g->nx - 1) * g->dx, (g->ny - 1) * g->dy);
   const double zmin = g->sod - r, rho = r / zmin;
   const char* env = std::getenv("FDK_BP_KERNEL");
   if (env && std::strcmp(env, "direct") == 0) return ts;  // vc = 0: direct variant
-  const double kmax = gc.cz + kBrickZ;
+  const double kmax = gc.cz + bz;
   double wu = 0.0, wv = 0.0;
   for (int32_t s = 0; s < vb.nviews; ++s) {
     // |sin| and |cos| of the view from its geometry: ci = sin Dx, cj = -cos Dy.
@@ -383,7 +421,7 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
     const double duj = gc.ku * g->dy * (as + ac * rho) / zmin;
     wu = std::fmax(wu, (kBrickX - 1) * dui + (kBrickY - 1) * duj);
     const double dz = (kBrickX - 1) * g->dx * as + (kBrickY - 1) * g->dy * ac;
-    wv = std::fmax(wv, gc.kv * ((kBrickZ - 1) / zmin + kmax * dz / (zmin * zmin)));
+    wv = std::fmax(wv, gc.kv * ((bz - 1) / zmin + kmax * dz / (zmin * zmin)));
   }
   // floor() of the extremes adds one pixel, the second tap one row, the
   // origin margin one pixel, FP32 column arithmetic up to one more.
@@ -393,9 +431,9 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   if (ts.tu + 1 > kThreads) return ts;  // staging and the adjoint's flush: a thread per column
   ts.rstep = kThreads / ts.tu;
   ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
-  const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * kTileEntryBytes;
+  const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * entry_bytes;
   int64_t vc = std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);
-  vc = std::min<int64_t>(vc, kPrefetchSlots / ts.rows);
+  vc = std::min<int64_t>(vc, slots / ts.rows);
   if (const char* cap = std::getenv("FDK_BP_VC")) vc = std::min<int64_t>(vc, std::atoi(cap));
   ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
   return ts;

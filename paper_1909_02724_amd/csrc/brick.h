@@ -47,11 +47,13 @@ struct BrickView {
   int32_t inside;  // the tile (columns org_u .. org_u + tu, its rows and mirror rows) is on the detector
 };
 
+// bz: slices per brick; mirror: whether the tile also holds the mirror rows
+// (then `inside` requires them on the detector too).
 __device__ BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i_lo, int32_t i_hi,
                                  int32_t j_lo, int32_t j_hi, int32_t kb, int32_t tu = 0,
-                                 int32_t tv = 0) {
+                                 int32_t tv = 0, int32_t bz = kBrickZ, bool mirror = true) {
   const double k0 = static_cast<double>(kb) - gc.cz;
-  const double k1 = static_cast<double>(kb + kBrickZ - 1) - gc.cz;
+  const double k1 = static_cast<double>(kb + bz - 1) - gc.cz;
   // u is a ratio of functions affine in (i, j) and v is affine in k at
   // fixed f: over the brick's (i, j, k) box both are extremal at corners.
   double umin = INFINITY, vmin = INFINITY;
@@ -83,7 +85,7 @@ __device__ BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i
   const bool cols_in = b.org_u >= 0 && b.org_u + tu < gc.nu;
   const bool rows_in = b.org_v >= 0 && b.org_v + tv <= gc.nv;
   const bool mirror_in = gc.mirror_g - b.org_v < gc.nv && gc.mirror_g - b.org_v - tv + 1 >= 0;
-  b.inside = tu > 0 && cols_in && rows_in && mirror_in;
+  b.inside = tu > 0 && cols_in && rows_in && (!mirror || mirror_in);
   return b;
 }
 

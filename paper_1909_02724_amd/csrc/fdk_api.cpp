@@ -246,7 +246,11 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
     for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
     const char* qb = static_cast<const char*>(q) + (size_t)b * vstride * dtype_size(q_dtype);
     for (const fdk::SliceRun& r : sl.runs) {
-      const fdk::TileShape ts = fdk::tile_shape(g, gc, r, vb);
+      const fdk::TileShape ts =
+          r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
+                                     fdk::kPrefetchSlots)
+                   : fdk::tile_shape(g, gc, r, vb, fdk::kPlainBrickZ, fdk::kPlainEntryBytes,
+                                     fdk::kPlainPrefetchSlots);
       if (int e = fdk::launch_backproject(gc, r, vb, ts, qb, q_dtype, vstride, vol, scale,
                                           (b > 0) || acc0, stream))
         return fail(FDK_ERR_HIP, "back-projection launch failed: HIP error %d", e);
@@ -280,7 +284,8 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
     vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
     for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
     for (const fdk::SliceRun& r : sl.runs) {
-      const fdk::TileShape ts = fdk::tile_shape(g, gc, r, vb);
+      const fdk::TileShape ts = fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
+                                                fdk::kPrefetchSlots);
       if (int e = fdk::launch_forward_project(gc, r, vb, ts, vol, q + (size_t)b * vstride,
                                               vstride, scale, stream))
         return fail(FDK_ERR_HIP, "forward-projection launch failed: HIP error %d", e);

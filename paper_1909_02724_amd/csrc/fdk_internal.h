@@ -73,8 +73,16 @@ struct TileShape {
 // Kernel choice for a run and view batch: tiled unless the footprint tile
 // exceeds the LDS or prefetch budget (or FDK_BP_KERNEL=direct, a debugging
 // aid; FDK_BP_VC caps the views per stage, a tuning aid).
+// bz: slices per brick; entry_bytes: LDS bytes per tile entry; slots: tile
+// entries a thread prefetches per stage.
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
-                     const ViewBatch& vb);
+                     const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots);
+// Plain (unmirrored) back-projection runs: 32 slices per brick, the tile
+// holding (q, dq/du) of the main rows only; a prefetch slot holds one row's
+// pair instead of two, so twice as many fit the same registers.
+constexpr int kPlainBrickZ = 2 * kBrickZ;
+constexpr int kPlainEntryBytes = 8;
+constexpr int kPlainPrefetchSlots = 2 * kPrefetchSlots;
 
 // Launchers (defined in the .hip files). They return a hipError_t as int.
 int launch_backproject(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
