@@ -33,7 +33,7 @@ namespace fdk {
 namespace {
 
 constexpr int kFilterThreads = 256;
-constexpr int kFftMaxLog = 13;             // L <= 8192 complex points (68 KB of LDS)
+constexpr int kFftMaxLog = 13;             // L <= 8192 complex points (139 KB of LDS)
 constexpr int64_t kFftMaxGroups = 2048;    // workgroups of an FFT launch
 constexpr int kDirectMaxNu = 256;          // below this the direct kernel is cheaper
 constexpr int kDirectBlock = 128;          // taps per partial sum in the direct kernel
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
 }
 
 // ---- FFT path -------------------------------------------------------------
-// Stockham FFT of L = 2^LOGL points: every thread holds 16 points in
+// Stockham FFT of L = 2^LOGL points in FP64: every thread holds 16 points in
 // registers; a pass gathers R points strided by L/R, applies the twiddles
 // W^(r k), runs an R-point DFT in registers and scatters the results to their
 // autosorted places, through one padded LDS buffer per FFT. Passes are radix
@@ -126,6 +126,17 @@ __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
 // four (that pass needs no twiddles). The forward transform's first pass
 // reads the rows from global memory, the inverse transform's last pass writes
 // them, so a row pair crosses LDS 2 P - 1 times for P passes.
+//
+// Why FP64: the ramp filter removes most of a smooth row's content (its low
+// frequencies), so FP32 rounding in the transform, relative to the input's
+// size, is large relative to the output. On projections of ellipsoid
+// phantoms an FP32 transform misses the FP64 result by 1e-5 (512-pixel rows)
+// to 7e-5 (4096-pixel rows) rel-L2; in FP64 the output is the FP64 result
+// rounded. FP64 FMAs issue at the FP32 (non-packed) rate on this GPU; the
+// cost is LDS bytes and registers.
+using cx = double2;
+__device__ __forceinline__ cx make_cx(double x, double y) { return make_double2(x, y); }
+
 template <int LOGL>
 struct FftCfg {
   static constexpr int L = 1 << LOGL;
@@ -135,7 +146,9 @@ struct FftCfg {
   static constexpr int RR = 1 << (LOGL % 4);         // first-pass radix (1: none)
   static constexpr int NP = (RR > 1 ? 1 : 0) + LOGL / 4;  // passes
   static constexpr int BUF = L + L / 16;             // padded points per FFT
+  static constexpr int THI = L / 64;                 // twiddle table: W^(64 j), j < L/64
 };
+constexpr int kTwLo = 64;                            // and W^i, i < 64
 
 template <int LOGL, int IP>
 struct PassCfg {
@@ -150,34 +163,34 @@ struct PassCfg {
 // conflicts.
 __device__ __forceinline__ int32_t fpad(int32_t i) { return i + (i >> 4); }
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+__device__ __forceinline__ cx cmul(cx a, cx b) {
+  return make_cx(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
 
 // x W16^q with W16 = exp(-2 pi i / 16), q in [0, 8): exact rotations by
 // multiples of pi/2 and pi/4 use adds only.
-__device__ __forceinline__ float2 rot16(float2 x, int q) {
-  constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
-  constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
-  constexpr float h = 0.70710678118654752440f;   // sqrt(1/2)
+__device__ __forceinline__ cx rot16(cx x, int q) {
+  constexpr double c1 = 0.92387953251128675613;  // cos(pi/8)
+  constexpr double s1 = 0.38268343236508977173;  // sin(pi/8)
+  constexpr double h = 0.70710678118654752440;   // sqrt(1/2)
   switch (q) {
     case 0: return x;
-    case 1: return make_float2(fmaf(x.x, c1, x.y * s1), fmaf(x.y, c1, -x.x * s1));
-    case 2: return make_float2((x.x + x.y) * h, (x.y - x.x) * h);
-    case 3: return make_float2(fmaf(x.x, s1, x.y * c1), fmaf(x.y, s1, -x.x * c1));
-    case 4: return make_float2(x.y, -x.x);
-    case 5: return make_float2(fmaf(x.y, c1, -x.x * s1), -fmaf(x.x, c1, x.y * s1));
-    case 6: return make_float2((x.y - x.x) * h, -(x.x + x.y) * h);
-    default: return make_float2(fmaf(x.y, s1, -x.x * c1), -fmaf(x.x, s1, x.y * c1));
+    case 1: return make_cx(fma(x.x, c1, x.y * s1), fma(x.y, c1, -x.x * s1));
+    case 2: return make_cx((x.x + x.y) * h, (x.y - x.x) * h);
+    case 3: return make_cx(fma(x.x, s1, x.y * c1), fma(x.y, s1, -x.x * c1));
+    case 4: return make_cx(x.y, -x.x);
+    case 5: return make_cx(fma(x.y, c1, -x.x * s1), -fma(x.x, c1, x.y * s1));
+    case 6: return make_cx((x.y - x.x) * h, -(x.x + x.y) * h);
+    default: return make_cx(fma(x.y, s1, -x.x * c1), -fma(x.x, s1, x.y * c1));
   }
 }
 
 // In-register DFT of v[0, N), N in {2, 4, 8, 16}, natural order in and out:
 // radix-2 decimation in time on the bit-reversed copy.
 template <int N>
-__device__ __forceinline__ void dft_reg(float2* v) {
+__device__ __forceinline__ void dft_reg(cx* v) {
   constexpr int LOGN = N == 2 ? 1 : N == 4 ? 2 : N == 8 ? 3 : 4;
-  float2 a[N];
+  cx a[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     int r = 0;
@@ -191,10 +204,10 @@ __device__ __forceinline__ void dft_reg(float2* v) {
     for (int i = 0; i < N; i += 2 * h) {
 #pragma unroll
       for (int p = 0; p < h; ++p) {
-        const float2 t = rot16(a[i + p + h], p * (16 / (2 * h)));
-        const float2 u = a[i + p];
-        a[i + p] = make_float2(u.x + t.x, u.y + t.y);
-        a[i + p + h] = make_float2(u.x - t.x, u.y - t.y);
+        const cx t = rot16(a[i + p + h], p * (16 / (2 * h)));
+        const cx u = a[i + p];
+        a[i + p] = make_cx(u.x + t.x, u.y + t.y);
+        a[i + p + h] = make_cx(u.x - t.x, u.y - t.y);
       }
     }
   }
@@ -202,25 +215,17 @@ __device__ __forceinline__ void dft_reg(float2* v) {
   for (int i = 0; i < N; ++i) v[i] = a[i];
 }
 
-// Base twiddles W^(k 2^b), b < 4, of the radix-16 pass IP for thread t,
-// W = exp(-2 pi i / L), k = (t mod NS) L / (16 NS); rounded from FP64.
-template <int LOGL, int IP>
-__device__ __forceinline__ void pass_twiddles(int32_t t, float2* w) {
-  using P = PassCfg<LOGL, IP>;
-  const int32_t k = (t % P::NS) * (FftCfg<LOGL>::L / (16 * P::NS));
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    double sv, cv;
-    sincospi(-2.0 * static_cast<double>(k << b) / FftCfg<LOGL>::L, &sv, &cv);
-    w[b] = make_float2(static_cast<float>(cv), static_cast<float>(sv));
-  }
+// W^m, W = exp(-2 pi i / L), m < L: the product of two table entries.
+__device__ __forceinline__ cx twiddle(const cx* thi, const cx* tlo, int32_t m) {
+  return cmul(thi[m >> 6], tlo[m & (kTwLo - 1)]);
 }
 
-// v[r] *= W^(r k) for r in [1, 16), from the base twiddles (at most three
-// products deep).
-__device__ __forceinline__ void apply_twiddles(float2* v, const float2* w) {
-  const float2 w1 = w[0], w2 = w[1], w4 = w[2], w8 = w[3];
-  const float2 w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+// v[r] *= W^(r k) for r in [1, 16): the base twiddles W^(k 2^b), b < 4,
+// from the table, the rest as products at most three deep.
+__device__ __forceinline__ void apply_twiddles(cx* v, const cx* thi, const cx* tlo, int32_t k) {
+  const cx w1 = twiddle(thi, tlo, k), w2 = twiddle(thi, tlo, 2 * k);
+  const cx w4 = twiddle(thi, tlo, 4 * k), w8 = twiddle(thi, tlo, 8 * k);
+  const cx w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
   v[1] = cmul(v[1], w1);
   v[2] = cmul(v[2], w2);
   v[3] = cmul(v[3], w3);
@@ -253,17 +258,20 @@ __device__ __forceinline__ int32_t scatter_index(int32_t j, int r) {
   return (j / P::NS) * (P::NS * P::R) + (j % P::NS) + r * P::NS;
 }
 
-// Twiddle, DFT and scatter of pass IP; v holds the gathered points.
+// Twiddle and DFT of pass IP; v holds the gathered points. Passes with
+// NS > 1 are radix 16 with one butterfly per thread (j = t), twiddle
+// exponent k = (t mod NS) L / (16 NS).
 template <int LOGL, int IP>
-__device__ __forceinline__ void pass_compute(float2* v, const float2 (*tw)[4]) {
+__device__ __forceinline__ void pass_compute(cx* v, int32_t t, const cx* thi, const cx* tlo) {
   using P = PassCfg<LOGL, IP>;
-  if constexpr (P::NS > 1) apply_twiddles(v, tw[IP]);
+  if constexpr (P::NS > 1)
+    apply_twiddles(v, thi, tlo, (t % P::NS) * (FftCfg<LOGL>::L / (16 * P::NS)));
 #pragma unroll
   for (int m = 0; m < P::B; ++m) dft_reg<P::R>(v + m * P::R);
 }
 
 template <int LOGL, int IP>
-__device__ __forceinline__ void pass_scatter_lds(float2* buf, int32_t t, const float2* v) {
+__device__ __forceinline__ void pass_scatter_lds(cx* buf, int32_t t, const cx* v) {
   using P = PassCfg<LOGL, IP>;
 #pragma unroll
   for (int m = 0; m < P::B; ++m)
@@ -273,7 +281,7 @@ __device__ __forceinline__ void pass_scatter_lds(float2* buf, int32_t t, const f
 }
 
 template <int LOGL, int IP>
-__device__ __forceinline__ void pass_gather_lds(const float2* buf, int32_t t, float2* v) {
+__device__ __forceinline__ void pass_gather_lds(const cx* buf, int32_t t, cx* v) {
   using P = PassCfg<LOGL, IP>;
 #pragma unroll
   for (int m = 0; m < P::B; ++m)
@@ -285,29 +293,33 @@ __device__ __forceinline__ void pass_gather_lds(const float2* buf, int32_t t, fl
 // for pass IP). The last pass leaves its results in v, in the order of
 // scatter_index; every earlier pass crosses LDS.
 template <int LOGL, int IP>
-__device__ __forceinline__ void fft_rest(float2* buf, int32_t t, float2* v, const float2 (*tw)[4]) {
-  pass_compute<LOGL, IP>(v, tw);
+__device__ __forceinline__ void fft_rest(cx* buf, int32_t t, cx* v, const cx* thi, const cx* tlo) {
+  pass_compute<LOGL, IP>(v, t, thi, tlo);
   if constexpr (IP + 1 < FftCfg<LOGL>::NP) {
     __syncthreads();  // the buffer's previous contents are read
     pass_scatter_lds<LOGL, IP>(buf, t, v);
     __syncthreads();
     pass_gather_lds<LOGL, IP + 1>(buf, t, v);
-    fft_rest<LOGL, IP + 1>(buf, t, v, tw);
+    fft_rest<LOGL, IP + 1>(buf, t, v, thi, tlo);
   }
 }
 
-// Cosine weight of pixel a on a row: D rsqrt(D^2 + ((b - cv) dv)^2 + ((a - cu) du)^2),
-// the row's share precomputed.
+// Cosine weight of pixel a on a row: D / sqrt(D^2 + ((b - cv) dv)^2 + ((a - cu) du)^2),
+// the row's share precomputed; an FP32 reciprocal square root refined by
+// one Newton step in FP64.
 struct RowWeight {
-  float d, base;
+  double d, base;
 };
 __device__ __forceinline__ RowWeight row_weight(const GeoConst& gc, double dv, double sdd, int32_t b) {
   const double bb = (b - gc.cv) * dv;
-  return RowWeight{static_cast<float>(sdd), static_cast<float>(sdd * sdd + bb * bb)};
+  return RowWeight{sdd, sdd * sdd + bb * bb};
 }
-__device__ __forceinline__ float pixel_weight(RowWeight rw, float cu, float du, int32_t a) {
-  const float x = (static_cast<float>(a) - cu) * du;
-  return rw.d * __frsqrt_rn(fmaf(x, x, rw.base));
+__device__ __forceinline__ double pixel_weight(RowWeight rw, double cu, double du, int32_t a) {
+  const double x = (static_cast<double>(a) - cu) * du;
+  const double s = fma(x, x, rw.base);
+  const double r0 = static_cast<double>(__frsqrt_rn(static_cast<float>(s)));
+  const double r1 = r0 * fma(-0.5 * s, r0 * r0, 1.5);
+  return rw.d * r1;
 }
 
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer descriptor, gfx9 family
@@ -342,44 +354,48 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
     int64_t nrows, const float* __restrict__ e, OutT* __restrict__ q) {
   using C = FftCfg<LOGL>;
   constexpr int P0R = PassCfg<LOGL, 0>::R;
-  extern __shared__ float2 fbuf[];
+  extern __shared__ cx fbuf[];
   const int32_t g = static_cast<int32_t>(threadIdx.x) / C::TPF;
   const int32_t t = static_cast<int32_t>(threadIdx.x) % C::TPF;
-  float2* buf = fbuf + g * C::BUF;
+  cx* buf = fbuf + g * C::BUF;
+  cx* thi = fbuf + C::G * C::BUF;  // twiddle tables after the FFT buffers
+  cx* tlo = thi + C::THI;
   const int32_t nu = gc.nu;
-  const float cuf = static_cast<float>(gc.cu), duf = static_cast<float>(du);
+  const double cu = gc.cu;
 
-  float2 tw[C::NP][4];
-#pragma unroll
-  for (int ip = 0; ip < C::NP; ++ip) tw[ip][0] = tw[ip][1] = tw[ip][2] = tw[ip][3] = make_float2(1.0f, 0.0f);
-  if constexpr (C::NP > 1) pass_twiddles<LOGL, 1>(t, tw[1]);
-  if constexpr (C::NP > 2) pass_twiddles<LOGL, 2>(t, tw[2]);
-  if constexpr (C::NP > 3) pass_twiddles<LOGL, 3>(t, tw[3]);
-  // The first pass never needs twiddles (NS = 1).
+  for (int32_t i = threadIdx.x; i < C::THI + kTwLo; i += C::WG) {
+    const int32_t m = i < C::THI ? 64 * i : i - C::THI;
+    double sv, cv;
+    sincospi(-2.0 * static_cast<double>(m) / C::L, &sv, &cv);
+    thi[i] = make_cx(cv, sv);  // tlo follows thi contiguously
+  }
+  __syncthreads();
 
   // Kernel spectrum: FFT of the taps tau h(m), |m| < Nu, placed circularly;
-  // each thread keeps H at the points it gathers in the inverse's first pass.
-  float2 v[16];
+  // each thread keeps H (rounded to FP32) at the points it gathers in the
+  // inverse's first pass.
+  cx v[16];
 #pragma unroll
   for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
 #pragma unroll
     for (int r = 0; r < P0R; ++r) {
       const int32_t n = gather_index<LOGL, 0>(t, m, r);
       const int32_t s = n < C::L / 2 ? n : n - C::L;
-      const float hv = (s > -nu && s < nu) ? static_cast<float>(tau * ramp_tap(kind, s, tau)) : 0.0f;
-      v[m * P0R + r] = make_float2(hv, 0.0f);
+      const double hv = (s > -nu && s < nu) ? tau * ramp_tap(kind, s, tau) : 0.0;
+      v[m * P0R + r] = make_cx(hv, 0.0);
     }
-  fft_rest<LOGL, 0>(buf, t, v, tw);
+  fft_rest<LOGL, 0>(buf, t, v, thi, tlo);
   __syncthreads();
   pass_scatter_lds<LOGL, C::NP - 1>(buf, t, v);
   __syncthreads();
   float H[16];
   {
-    constexpr float inv_l = 1.0f / static_cast<float>(C::L);
+    constexpr double inv_l = 1.0 / static_cast<double>(C::L);
 #pragma unroll
     for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
 #pragma unroll
-      for (int r = 0; r < P0R; ++r) H[m * P0R + r] = buf[fpad(gather_index<LOGL, 0>(t, m, r))].x * inv_l;
+      for (int r = 0; r < P0R; ++r)
+        H[m * P0R + r] = static_cast<float>(buf[fpad(gather_index<LOGL, 0>(t, m, r))].x * inv_l);
   }
 
   // Row pairs are wave-uniform (an FFT spans whole waves), so each row is
@@ -409,29 +425,32 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
     for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
 #pragma unroll
       for (int r = 0; r < P0R; ++r) {
-        float re = 0.0f, im = 0.0f;
+        double re = 0.0, im = 0.0;
         if (r < P0R / 2) {
           const int32_t n = gather_index<LOGL, 0>(t, m, r);
           const uint32_t off = static_cast<uint32_t>(n) * 4u;
           re = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ia, off, 0, 0));
           im = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ib, off, 0, 0));
           if (!ADJ) {
-            re *= pixel_weight(wa, cuf, duf, n);
-            im *= pixel_weight(wb, cuf, duf, n);
+            re *= pixel_weight(wa, cu, du, n);
+            im *= pixel_weight(wb, cu, du, n);
           }
         }
-        v[m * P0R + r] = make_float2(re, im);
+        v[m * P0R + r] = make_cx(re, im);
       }
     __syncthreads();  // the previous pair's last gather is done
-    fft_rest<LOGL, 0>(buf, t, v, tw);
+    fft_rest<LOGL, 0>(buf, t, v, thi, tlo);
     __syncthreads();
     pass_scatter_lds<LOGL, C::NP - 1>(buf, t, v);
     __syncthreads();
     // Inverse: conj(X) H gathered for the first pass.
     pass_gather_lds<LOGL, 0>(buf, t, v);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = make_float2(v[i].x * H[i], -v[i].y * H[i]);
-    fft_rest<LOGL, 0>(buf, t, v, tw);
+    for (int i = 0; i < 16; ++i) {
+      const double hi = H[i];
+      v[i] = make_cx(v[i].x * hi, -v[i].y * hi);
+    }
+    fft_rest<LOGL, 0>(buf, t, v, thi, tlo);
     // The last pass has one radix-16 butterfly per thread (j = t, NS = L/16):
     // result r is point t + r L/16, so the stores are coalesced; only the
     // lower half (r < 8) holds row pixels.
@@ -442,14 +461,14 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int32_t n = scatter_index<LOGL, C::NP - 1>(t, r);
-      float ya = v[r].x, yb = -v[r].y;
+      double ya = v[r].x, yb = -v[r].y;
       if (ADJ) {
-        ya *= pixel_weight(wa, cuf, duf, n);
-        yb *= pixel_weight(wb, cuf, duf, n);
+        ya *= pixel_weight(wa, cu, du, n);
+        yb *= pixel_weight(wb, cu, du, n);
       }
       const uint32_t off = static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(OutT));
-      buf_store_q(ya, oa, off, static_cast<OutT*>(nullptr));
-      buf_store_q(yb, ob, off, static_cast<OutT*>(nullptr));
+      buf_store_q(static_cast<float>(ya), oa, off, static_cast<OutT*>(nullptr));
+      buf_store_q(static_cast<float>(yb), ob, off, static_cast<OutT*>(nullptr));
     }
   }
 }
@@ -458,7 +477,7 @@ template <int LOGL, typename OutT, bool ADJ>
 int launch_fft(const GeoConst& gc, const RowBand& rb, double du, double dv, double sdd, double tau,
                int kind, int64_t nrows, const float* e, OutT* q, hipStream_t st) {
   using C = FftCfg<LOGL>;
-  const size_t lds = static_cast<size_t>(C::G) * C::BUF * sizeof(float2);
+  const size_t lds = (static_cast<size_t>(C::G) * C::BUF + C::THI + kTwLo) * sizeof(cx);
   auto kern = &filter_fft_kernel<LOGL, OutT, ADJ>;
   if (lds > 65536) {
     // Raised once per device and kernel, so launches recorded into a graph
