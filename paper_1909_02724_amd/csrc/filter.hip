@@ -36,7 +36,7 @@ constexpr int kFilterThreads = 256;
 constexpr int kFftMaxLog = 13;             // L <= 8192 complex points (139 KB of LDS)
 constexpr int64_t kFftMaxGroups = 2048;    // workgroups of an FFT launch
 constexpr int kDirectMaxNu = 256;          // below this the direct kernel is cheaper
-constexpr int kDirectBlock = 128;          // taps per partial sum in the direct kernel
+constexpr int kDirectMaxLds = 8192;        // widest row of the direct kernel (2 x 64 KB of LDS)
 
 // Ramp kernel h(n) at sample pitch tau: Ram-Lak (band-limited ramp) or
 // Shepp-Logan (ramp times sinc), FDK literature forms.
@@ -66,10 +66,10 @@ __device__ __forceinline__ void store_q(bf16_t* p, float x) {
 }
 
 // Cosine weight of pixel (a, b): D / sqrt(D^2 + ((a - cu) du)^2 + ((b - cv) dv)^2).
-__device__ __forceinline__ float cos_weight(const GeoConst& gc, double du, double dv, double sdd,
-                                            int32_t a, int32_t b) {
+__device__ __forceinline__ double cos_weight_f64(const GeoConst& gc, double du, double dv,
+                                                 double sdd, int32_t a, int32_t b) {
   const double aa = (a - gc.cu) * du, bb = (b - gc.cv) * dv;
-  return static_cast<float>(sdd / sqrt(sdd * sdd + aa * aa + bb * bb));
+  return sdd / sqrt(sdd * sdd + aa * aa + bb * bb);
 }
 
 // Row m of a band launch: input and output row pointers and detector row.
@@ -83,38 +83,52 @@ __device__ __forceinline__ BandRow band_row(const RowBand& rb, int32_t nu, int64
                  static_cast<int32_t>(rb.v0 + r)};
 }
 
+// Direct convolution, one workgroup per row, in FP64 (weighted row and
+// taps in LDS): like the FFT path, it keeps the output accurate on smooth
+// rows, whose filtered values are small next to the terms of the sum (an
+// FP32 sum misses by ~3e-5 rel-L2 on 5000-pixel phantom rows).
 template <typename OutT, bool ADJ>
 __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
     GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
     const float* __restrict__ e, OutT* __restrict__ q) {
-  extern __shared__ float lds[];
+  extern __shared__ double dlds[];
   const int32_t nu = gc.nu;
-  float* et = lds;      // cosine-weighted row
-  float* h = lds + nu;  // tau * h(|n|), n in [0, nu)
+  double* et = dlds;      // cosine-weighted row
+  double* h = dlds + nu;  // tau * h(|n|), n in [0, nu)
   const BandRow br = band_row(rband, nu, blockIdx.x);
   const int32_t b = br.b;
   const float* er = e + br.ein;
   for (int32_t a = threadIdx.x; a < nu; a += kFilterThreads) {
-    et[a] = ADJ ? er[a] : er[a] * cos_weight(gc, du, dv, sdd, a, b);
-    h[a] = static_cast<float>(tau * ramp_tap(kind, a, tau));
+    et[a] = ADJ ? static_cast<double>(er[a]) : er[a] * cos_weight_f64(gc, du, dv, sdd, a, b);
+    h[a] = tau * ramp_tap(kind, a, tau);
   }
   __syncthreads();
   OutT* qr = q + br.qout;
   for (int32_t a = threadIdx.x; a < nu; a += kFilterThreads) {
-    // Blocked sum: a serial FP32 sum over up to 8192 taps loses about
-    // 1e-5 relative; partial sums of kDirectBlock taps keep it near 2e-7.
-    float acc = 0.0f;
-    for (int32_t n0 = 0; n0 < nu; n0 += kDirectBlock) {
-      const int32_t n1 = min(nu, n0 + kDirectBlock);
-      float part = 0.0f;
-      for (int32_t n = n0; n < n1; ++n) {
-        const int32_t d = a - n;
-        part = fmaf(h[d < 0 ? -d : d], et[n], part);
-      }
-      acc += part;
+    double acc = 0.0;
+    for (int32_t n = 0; n < nu; ++n) {
+      const int32_t d = a - n;
+      acc = fma(h[d < 0 ? -d : d], et[n], acc);
     }
-    store_q(qr + a, ADJ ? acc * cos_weight(gc, du, dv, sdd, a, b) : acc);
+    store_q(qr + a, static_cast<float>(ADJ ? acc * cos_weight_f64(gc, du, dv, sdd, a, b) : acc));
   }
+}
+
+// Lets kernel K use more than the default 64 KB of dynamic LDS, once per
+// device, so launches recorded into a graph after the first (eager) call
+// make no attribute call.
+template <auto K>
+hipError_t raise_lds_limit(size_t bytes) {
+  static std::atomic<uint64_t> raised{0};
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
+  if (err != hipSuccess) return err;
+  const uint64_t bit = uint64_t{1} << (dev & 63);
+  if (raised.load(std::memory_order_acquire) & bit) return hipSuccess;
+  err = hipFuncSetAttribute(reinterpret_cast<const void*>(K),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+  if (err == hipSuccess) raised.fetch_or(bit, std::memory_order_release);
+  return err;
 }
 
 // ---- FFT path -------------------------------------------------------------
@@ -480,19 +494,8 @@ int launch_fft(const GeoConst& gc, const RowBand& rb, double du, double dv, doub
   const size_t lds = (static_cast<size_t>(C::G) * C::BUF + C::THI + kTwLo) * sizeof(cx);
   auto kern = &filter_fft_kernel<LOGL, OutT, ADJ>;
   if (lds > 65536) {
-    // Raised once per device and kernel, so launches recorded into a graph
-    // after the first (eager) call make no attribute call.
-    static std::atomic<uint64_t> raised{0};
-    int dev = 0;
-    hipError_t err = hipGetDevice(&dev);
+    const hipError_t err = raise_lds_limit<&filter_fft_kernel<LOGL, OutT, ADJ>>(lds);
     if (err != hipSuccess) return static_cast<int>(err);
-    const uint64_t bit = uint64_t{1} << (dev & 63);
-    if (!(raised.load(std::memory_order_acquire) & bit)) {
-      err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-      if (err != hipSuccess) return static_cast<int>(err);
-      raised.fetch_or(bit, std::memory_order_release);
-    }
   }
   // Workgroups loop over row pairs (H is computed once per workgroup): a
   // few per CU at most.
@@ -529,7 +532,12 @@ int launch_filter_t(const GeoConst& gc, const RowBand& rb, double du, double dv,
         default: err = launch_fft<13, OutT, ADJ>(gc, sub, du, dv, sdd, tau, kind, nrows, es, qs, st); break;
       }
     } else {
-      const size_t lds = 2 * static_cast<size_t>(gc.nu) * sizeof(float);
+      const size_t lds = 2 * static_cast<size_t>(gc.nu) * sizeof(double);
+      if (lds > 65536) {
+        const hipError_t e2 = raise_lds_limit<&filter_direct_kernel<OutT, ADJ>>(
+            2 * static_cast<size_t>(kDirectMaxLds) * sizeof(double));
+        if (e2 != hipSuccess) return static_cast<int>(e2);
+      }
       hipLaunchKernelGGL((filter_direct_kernel<OutT, ADJ>), dim3(static_cast<uint32_t>(nrows)),
                          dim3(kFilterThreads), lds, st, gc, sub, du, dv, sdd, tau, kind, es, qs);
       err = static_cast<int>(hipGetLastError());

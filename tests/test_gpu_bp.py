@@ -105,7 +105,7 @@ def test_filter_matches_oracle(kind, dtype):
     assert rel_l2(got, ref) <= tol
 
 
-@pytest.mark.parametrize("nu", [512, 2048, 4096])
+@pytest.mark.parametrize("nu", [200, 512, 2048, 4096, 5000])  # direct, FFT x3, direct
 def test_filter_on_phantom_rows_matches_oracle(nu):
     """Smooth rows are the hard case for the ramp filter: it removes most of
     their (low-frequency) content, so rounding in the transform, relative to
