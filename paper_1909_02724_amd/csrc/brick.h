@@ -142,7 +142,7 @@ struct BrickCoords {
 };
 
 __device__ __forceinline__ BrickCoords brick_coords(const GeoConst& gc, const SliceRun& run,
-                                                    const TileShape& ts) {
+                                                    const TileShape& ts, int32_t bz = kBrickZ) {
   const uint32_t nwg = gridDim.x;
   uint32_t lin = blockIdx.x;
   if ((nwg & 7u) == 0) lin = (lin & 7u) * (nwg >> 3) + (lin >> 3);
@@ -161,7 +161,7 @@ __device__ __forceinline__ BrickCoords brick_coords(const GeoConst& gc, const Sl
   bc.j = min(bc.j_lo + ty0, bc.j_hi);
   bc.txf = static_cast<float>(bc.i - bc.i_lo);
   bc.tyf = static_cast<float>(bc.j - bc.j_lo);
-  bc.t0 = seg * kBrickZ;
+  bc.t0 = seg * bz;
   bc.kb = run.k_first + bc.t0;
   return bc;
 }

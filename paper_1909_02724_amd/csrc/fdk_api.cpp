@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <limits>
 #include <string>
 #include <utility>
 #include <vector>
@@ -284,8 +285,13 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
     vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
     for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
     for (const fdk::SliceRun& r : sl.runs) {
-      const fdk::TileShape ts = fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
-                                                fdk::kPrefetchSlots);
+      // Plain runs: 32-slice bricks and a single accumulation plane; their
+      // flush has no prefetch budget to respect.
+      const fdk::TileShape ts =
+          r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
+                                     fdk::kPrefetchSlots)
+                   : fdk::tile_shape(g, gc, r, vb, fdk::kPlainBrickZ, fdk::kPlainEntryBytes,
+                                     std::numeric_limits<int32_t>::max());
       if (int e = fdk::launch_forward_project(gc, r, vb, ts, vol, q + (size_t)b * vstride,
                                               vstride, scale, stream))
         return fail(FDK_ERR_HIP, "forward-projection launch failed: HIP error %d", e);

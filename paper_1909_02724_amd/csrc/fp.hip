@@ -46,7 +46,8 @@ __device__ __forceinline__ uint32_t slot_rotation() {
 }
 
 // Voxel values of the thread's column, scaled, in the lane's slot order:
-// x[t] is slot (t + rot) mod 16.
+// x[t] is slot sl = (t + rot) mod 16; xm[t] is its mirror (mirrored runs)
+// or slot 16 + sl (plain runs, whose bricks hold 32 slices).
 template <bool MIRROR>
 __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& run,
                                             const BrickCoords& bc, const float* __restrict__ vol,
@@ -58,9 +59,13 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
     const int32_t sl = static_cast<int32_t>((t + rot) & (kBrickZ - 1));
     const bool in = bc.owner && (bc.t0 + sl < run.n);
     x[t] = in ? scale * vol[static_cast<int64_t>(run.loc_lo + bc.t0 + sl) * slice + col] : 0.0f;
-    xm[t] = (MIRROR && in)
-                ? scale * vol[static_cast<int64_t>(run.loc_hi - bc.t0 - sl) * slice + col]
-                : 0.0f;
+    if (MIRROR) {
+      xm[t] = in ? scale * vol[static_cast<int64_t>(run.loc_hi - bc.t0 - sl) * slice + col] : 0.0f;
+    } else {
+      const bool in2 = bc.owner && (bc.t0 + kBrickZ + sl < run.n);
+      xm[t] = in2 ? scale * vol[static_cast<int64_t>(run.loc_lo + bc.t0 + kBrickZ + sl) * slice + col]
+                  : 0.0f;
+    }
   }
 }
 
@@ -71,9 +76,10 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
 // and view from a bound on what one pixel can receive:
 //  - a column adds to the pixel columns floor(u) and floor(u) + 1, so pixel
 //    column p hears only from columns with floor(u) in {p - 1, p};
-//  - of a column's 16 slots, those with a tap on row r have v in [r - 1,
-//    r + 1): at most floor(2 / (dv/dk)) + 2 of them (one spare for the
-//    rounding of v), and never more than 16;
+//  - of a column's slices in the brick (16, or 32 for a plain run), those
+//    with a tap on row r have v in [r - 1, r + 1): at most
+//    floor(2 / (dv/dk)) + 2 of them (one spare for the rounding of v), and
+//    never more than the brick's slice count;
 //  - each contribution is at most M = max over columns of max|x| * W.
 // A histogram over floor(u) of the per-column slot bounds gives K, the most
 // contributions any pixel can receive, and S = 2^31 / (1.01 K M) keeps
@@ -95,6 +101,7 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
   __shared__ uint32_t amax_bits;
   const int32_t tid = threadIdx.x;
+  constexpr int BZ = MIRROR ? kBrickZ : kPlainBrickZ;  // slices per brick
   // blockIdx.y picks this workgroup's share of the launch's views: small
   // volumes split the views over several workgroups per brick (the
   // projections take their sums through atomics either way), so the grid
@@ -103,10 +110,11 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   const int32_t v_lo = static_cast<int32_t>(blockIdx.y) * per;
   const int32_t v_hi = min(vb.nviews, v_lo + per);
   if (v_lo >= v_hi) return;  // uniform, before any barrier
-  const BrickCoords bc = brick_coords(gc, run, ts);
+  const BrickCoords bc = brick_coords(gc, run, ts, BZ);
   if (tid == 0) amax_bits = 0u;
   if (tid >= v_lo && tid < v_hi)
-    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
+                           MIRROR);
   const uint32_t rot = slot_rotation();
   float x[kBrickZ], xm[kBrickZ];
   load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
       for (int32_t sl = 0; sl < nvc; ++sl) {
         const ColumnF32 c = column_f32(bvs[s0 + sl], bc.txf, bc.tyf, kvf);
         const uint32_t nu = min(c.nu, static_cast<uint32_t>(ts.tu - 1));
-        const float ks = fminf(static_cast<float>(kBrickZ), floorf(2.0f / c.dvk) + 2.0f);
+        const float ks = fminf(static_cast<float>(BZ), floorf(2.0f / c.dvk) + 2.0f);
         atomicAdd(&hist[sl * kHistStride + nu], static_cast<uint32_t>(ks));
         atomicMax(&mbits[sl], __float_as_uint(amax * c.w));
       }
@@ -185,6 +193,18 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
             atomicAdd(mbase1 + dn, __float2int_rn(ma * c.du));
             atomicAdd(mbase + dn + 1, __float2int_rn(mb * du0));
             atomicAdd(mbase1 + dn + 1, __float2int_rn(mb * c.du));
+          } else {
+            // The brick's upper 16 slices, into the same plane.
+            uint32_t dn2;
+            float fr2;
+            voxel_row_off(c.fvb, c.dvk, kBrickZ + static_cast<int32_t>((t + rot) & (kBrickZ - 1)),
+                          &dn2, &fr2);
+            const float v2 = ws * xm[t];
+            const float a2 = v2 - v2 * fr2, b2 = v2 * fr2;
+            atomicAdd(base + dn2, __float2int_rn(a2 * du0));
+            atomicAdd(base1 + dn2, __float2int_rn(a2 * c.du));
+            atomicAdd(base + dn2 + 1, __float2int_rn(b2 * du0));
+            atomicAdd(base1 + dn2 + 1, __float2int_rn(b2 * c.du));
           }
         }
       }
@@ -228,9 +248,11 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
                                                              int64_t vstride, float scale) {
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
   const int32_t tid = threadIdx.x;
-  const BrickCoords bc = brick_coords(gc, run, ts);
+  constexpr int BZ = MIRROR ? kBrickZ : kPlainBrickZ;  // slices per brick
+  const BrickCoords bc = brick_coords(gc, run, ts, BZ);
   if (tid < vb.nviews)
-    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb);
+    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
+                           MIRROR);
   const uint32_t rot = slot_rotation();
   float x[kBrickZ], xm[kBrickZ];
   load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
@@ -253,6 +275,12 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
       if (MIRROR) {
         const int32_t m = gc.mirror_g - n;
         splat(qs, gc.nu, gc.nv, a, c.du, m, m - 1, fr, c.w * xm[t]);
+      } else if (bc.t0 + kBrickZ + sl < run.n) {
+        uint32_t dn2;
+        float fr2;
+        voxel_row_off(c.fvb, c.dvk, kBrickZ + sl, &dn2, &fr2);
+        const int32_t n2 = nb + static_cast<int32_t>(dn2);
+        splat(qs, gc.nu, gc.nv, a, c.du, n2, n2 + 1, fr2, c.w * xm[t]);
       }
     }
   }
@@ -281,11 +309,15 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
     if (const char* env = std::getenv("FDK_FP_VSPLIT")) vsplit = std::atoi(env);
     vsplit = std::max<int64_t>(1, std::min<int64_t>(vsplit, vb.nviews));
     const dim3 grid(static_cast<uint32_t>(nwg), static_cast<uint32_t>(vsplit));
-    // Adjoint tile: one more column than the back-projection tile, float2
-    // entries; it always fits where the back-projection tile does.
+    // Adjoint tile: one more column than the back-projection tile, one
+    // 32-bit word per pixel and plane (main, plus mirror for mirrored runs).
+    // The host sizes the back-projection tile at 16 (mirrored) or 8 (plain)
+    // bytes per entry, so at least one view's tile always fits.
     TileShape tf = ts;
-    const int64_t per_view = static_cast<int64_t>(ts.tu + 1) * ts.tvp * sizeof(int2);
+    const int64_t per_view =
+        static_cast<int64_t>(ts.tu + 1) * ts.tvp * sizeof(int) * (run.mirror ? 2 : 1);
     tf.vc = static_cast<int32_t>(std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view));
+    if (tf.vc < 1) return static_cast<int>(hipErrorInvalidValue);
     const size_t lds = static_cast<size_t>(tf.vc) * per_view;
     if (run.mirror)
       hipLaunchKernelGGL((fp_tiled_kernel<true>), grid, block, lds, st, gc, run, vb, tf, vol,

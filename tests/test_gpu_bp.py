@@ -223,9 +223,15 @@ def test_bp_bitwise_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("name", ["ragged_even", "ragged_odd", "offset_half", "offset_frac"])
+# Plain runs put 32 slices in a brick: 37 and 70 slices leave ragged tops.
+ADJ_VARIANTS = dict(VARIANTS, plain_odd=BASE.replace(nz=37, off_v=0.27),
+                    plain_tall=BASE.replace(nz=70, off_u=0.2, off_v=-0.4, nv=90))
+
+
+@pytest.mark.parametrize("name", ["ragged_even", "ragged_odd", "offset_half", "offset_frac",
+                                  "plain_odd", "plain_tall"])
 def test_adjoint_matches_oracle_and_dot_test(name):
-    g = VARIANTS[name]
+    g = ADJ_VARIANTS[name]
     ang = synth.angles(37, start=0.2)
     rng = np.random.default_rng(21)
     x = rng.standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
@@ -309,6 +315,21 @@ def test_tiled_kernel_agrees_with_direct_kernel(name, monkeypatch):
     announce(f"  tiled vs direct: rel-L2 {err:.3e}, max |diff| {np.abs(a - b).max():.3e} "
              f"(max |v| {np.abs(b).max():.3e})")
     assert err <= 5e-6
+
+
+@pytest.mark.parametrize("name", ["ragged_odd", "offset_frac", "plain_odd", "plain_tall"])
+def test_adjoint_direct_kernel_matches_oracle(name, monkeypatch):
+    """The adjoint's direct kernel (FP64 columns, global atomics), used
+    where a footprint tile does not fit LDS, against the oracle."""
+    g = ADJ_VARIANTS[name]
+    ang = synth.angles(37, start=0.2)
+    x = np.random.default_rng(22).standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
+    monkeypatch.setenv("FDK_BP_KERNEL", "direct")
+    fp = host(fdk.forward_project(gpu(x), g, ang, scale=0.8))
+    ref = oracle.forward_project(g, ang, x.astype(np.float64), scale=0.8)
+    err = rel_l2(fp, ref)
+    announce(f"  direct adjoint {name}: rel-L2 {err:.3e}")
+    assert err <= 1e-5
 
 
 # Geometries for the footprint-tile bounds: strong magnification (tiles do
