@@ -108,30 +108,31 @@ def test_bp2048_full_size_sampled():
         assert e_f32 <= 2e-3
 
 
-def test_adjoint_2048_dot_full_size():
+@pytest.mark.parametrize("off_v,nviews", [(0.0, 256), (0.27, 64)], ids=["mirrored", "plain"])
+def test_adjoint_2048_dot_full_size(off_v, nviews):
     """The adjoint in the benchmark's adjoint configuration (2048^3, 256
-    views of 2048^2, 32 views per launch): <B q, x> = <q, F x> on positive
-    data to 1e-6 relative, inner products in FP64 slab by slab. B is pinned
-    to the oracle at this size by test_bp2048_full_size_sampled, so this
-    checks F there as its transpose."""
+    views of 2048^2 spread over the circle, 32 views per launch), and on
+    plain slice runs (off_v = 0.27: no pixel-aligned mirror, 32-slice
+    bricks): <B q, x> = <q, F x> on positive data to 1e-6 relative, inner
+    products in FP64 slab by slab. B is pinned to the oracle at this size by
+    test_bp2048_full_size_sampled, so this checks F there as its transpose."""
     import synth.gpu as sg
     c = synth.config("bp2048")
-    g = c["geom"]
-    ang = synth.angles(c["np"])
-    nviews = 256
-    announce("adjoint 2048: filling 4 GiB of projections and a 32 GiB volume")
+    g = c["geom"].replace(off_v=off_v)
+    ang = np.ascontiguousarray(synth.angles(c["np"])[:: c["np"] // nviews])
+    announce(f"adjoint 2048 off_v {off_v}: filling projections and a 32 GiB volume")
     q = sg.hash_fill(torch.empty((nviews, g.nv, g.nu), dtype=torch.float32, device=DEV), 4096)
     q.add_(1.5)
     x = sg.hash_fill(torch.empty((g.nz, g.ny, g.nx), dtype=torch.float32, device=DEV), 4097)
     x.add_(1.5)
-    announce("adjoint 2048: back-projection of 256 views")
+    announce(f"adjoint 2048: back-projection of {nviews} views")
     bq = fdk.backproject(q, g, ang)
     lhs = 0.0
     for k0 in range(0, g.nz, 64):
         lhs += float((bq[k0:k0 + 64].double() * x[k0:k0 + 64].double()).sum())
     del bq
     torch.cuda.empty_cache()
-    announce("adjoint 2048: forward projection of 256 views")
+    announce(f"adjoint 2048: forward projection of {nviews} views")
     fx = fdk.forward_project(x, g, ang, nviews=nviews)
     rhs = 0.0
     for s0 in range(0, nviews, 32):
