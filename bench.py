@@ -50,7 +50,7 @@ METRIC = "back-projection GUPS at 2048³/2048 views; FP16-store vs FP32; adjoint
 # Chip constants (MI355X, gfx950): 256 CUs at 2.4 GHz; a SIMD retires one
 # 64-lane FP32 VALU instruction per 4 clocks, 4 SIMDs per CU -> 64 lane-ops/clk/CU.
 N_CU, CLOCK_HZ, VALU_LANES_PER_CLK = 256, 2.4e9, 64
-# LDS read bandwidth measured with lds_probe.hip on MI355X: 93.2 TB/s,
+# LDS read bandwidth measured with probes/lds_probe.hip on MI355X: 93.2 TB/s,
 # 151.7 B/clk/CU at 2.4 GHz (above the 128 B/clk of the previous generation).
 LDS_BYTES_PER_CLK = 151.7
 HBM_PEAK = 8.0e12
