@@ -317,15 +317,32 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   if (!owner) return;
   const int64_t slice = static_cast<int64_t>(gc.nx) * gc.ny;
   const int64_t col = static_cast<int64_t>(j) * gc.nx + i;
+  float* const lo = vol + static_cast<int64_t>(run.loc_lo + t0) * slice + col;
+  float* const hi = vol + static_cast<int64_t>(run.loc_hi - t0) * slice + col;
+  const int32_t nt = min(BZ, run.n - t0);  // slices of the brick in the run
+  // All old values are read before the first store: interleaved, each read
+  // would wait out a full memory round trip, since the compiler cannot tell
+  // that a store does not alias the next read.
+  float old[BZ], oldm[kBrickZ];
 #pragma unroll
   for (int t = 0; t < BZ; ++t) {
-    if (t0 + t >= run.n) break;
-    float* p = vol + static_cast<int64_t>(run.loc_lo + t0 + t) * slice + col;
-    *p = accumulate ? fmaf(scale, slice_acc(t), *p) : scale * slice_acc(t);
-    if (MIRROR) {
-      float* pm = vol + static_cast<int64_t>(run.loc_hi - t0 - t) * slice + col;
-      *pm = accumulate ? fmaf(scale, accm[t], *pm) : scale * accm[t];
+    old[t] = 0.0f;
+    if (t < kBrickZ) oldm[t] = 0.0f;
+  }
+  if (accumulate) {
+#pragma unroll
+    for (int t = 0; t < BZ; ++t) {
+      if (t < nt) {
+        old[t] = lo[static_cast<int64_t>(t) * slice];
+        if (MIRROR) oldm[t] = hi[-static_cast<int64_t>(t) * slice];
+      }
     }
+  }
+#pragma unroll
+  for (int t = 0; t < BZ; ++t) {
+    if (t >= nt) break;
+    lo[static_cast<int64_t>(t) * slice] = fmaf(scale, slice_acc(t), old[t]);
+    if (MIRROR) hi[-static_cast<int64_t>(t) * slice] = fmaf(scale, accm[t], oldm[t]);
   }
 }
 
