@@ -356,7 +356,8 @@ def run_filter(dev):
 
 def run_ablation(dev):
     """What each part of the kernel's design contributes, on the 2048^3
-    geometry with 64 views of FP32 projections: the tiled kernel with
+    geometry with 64 views of FP32 projections spread evenly over the circle
+    (the kernels' speed varies with the view angle): the tiled kernel with
     mirror pairs (Theorem 1), the same without mirror pairs (a fractional
     principal-point offset leaves no pixel-aligned mirror, so every slice is
     back-projected on its own), and the direct variant (taps read from
@@ -367,9 +368,11 @@ def run_ablation(dev):
     import synth
     import synth.gpu as sg
 
+    import numpy as np
+
     c = synth.config("bp2048")
-    g0, ang = c["geom"], synth.angles(c["np"])
     n = 64
+    g0, ang = c["geom"], np.ascontiguousarray(synth.angles(c["np"])[:: c["np"] // n])
     q = sg.hash_fill(torch.empty((n, g0.nv, g0.nu), dtype=torch.float32, device=dev), 5)
     vol = torch.empty((g0.nz, g0.ny, g0.nx), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
