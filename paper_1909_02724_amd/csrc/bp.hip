@@ -322,27 +322,22 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   const int32_t nt = min(BZ, run.n - t0);  // slices of the brick in the run
   // All old values are read before the first store: interleaved, each read
   // would wait out a full memory round trip, since the compiler cannot tell
-  // that a store does not alias the next read.
+  // that a store does not alias the next read. (Written this way, with the
+  // reads selected rather than guarded, the plain variant also keeps its
+  // accumulators out of scratch inside the view loop.)
   float old[BZ], oldm[kBrickZ];
 #pragma unroll
   for (int t = 0; t < BZ; ++t) {
-    old[t] = 0.0f;
-    if (t < kBrickZ) oldm[t] = 0.0f;
-  }
-  if (accumulate) {
-#pragma unroll
-    for (int t = 0; t < BZ; ++t) {
-      if (t < nt) {
-        old[t] = lo[static_cast<int64_t>(t) * slice];
-        if (MIRROR) oldm[t] = hi[-static_cast<int64_t>(t) * slice];
-      }
-    }
+    old[t] = (accumulate && t < nt) ? lo[static_cast<int64_t>(t) * slice] : 0.0f;
+    if (t < kBrickZ)
+      oldm[t] = (MIRROR && accumulate && t < nt) ? hi[-static_cast<int64_t>(t) * slice] : 0.0f;
   }
 #pragma unroll
   for (int t = 0; t < BZ; ++t) {
-    if (t >= nt) break;
-    lo[static_cast<int64_t>(t) * slice] = fmaf(scale, slice_acc(t), old[t]);
-    if (MIRROR) hi[-static_cast<int64_t>(t) * slice] = fmaf(scale, accm[t], oldm[t]);
+    if (t < nt) {
+      lo[static_cast<int64_t>(t) * slice] = fmaf(scale, slice_acc(t), old[t]);
+      if (MIRROR) hi[-static_cast<int64_t>(t) * slice] = fmaf(scale, accm[t], oldm[t]);
+    }
   }
 }
 
