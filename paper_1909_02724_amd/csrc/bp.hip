@@ -417,6 +417,8 @@ int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, co
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots) {
   TileShape ts{};
+  ts.rot_a = 1;
+  ts.rot_b = 4;
   ts.nbx = (gc.nx + kBrickX - 1) / kBrickX;
   ts.nby = (gc.ny + kBrickY - 1) / kBrickY;
   ts.nseg = (run.n + bz - 1) / bz;

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <limits>
 #include <string>
 #include <utility>
@@ -119,6 +120,95 @@ fdk::ViewGeo make_view(const fdk_geometry* g, double beta) {
   v.aj = s * g->dy;
   v.a0 = -c * g->dx * cx - s * g->dy * cy;
   return v;
+}
+
+// Adjoint slot rotation: the order in which each lane visits its 16 slots.
+// The tiled adjoint is bound by LDS bank conflicts among the 64 lanes of each
+// atomic add, and which rotation spreads them best depends on the view
+// angle (at 2048^3, 32-view batches took 201-339 ms with (tx + 4 ty) and
+// 201-248 ms with the best of four rotations). For large launches the host
+// scores the candidates with a model of the adds' addresses: per wave
+// instruction, the most lanes that fall in one of the 64 four-byte banks,
+// summed over sample bricks and views. A uniform shift of all addresses
+// leaves that count unchanged, so tile origins are not needed.
+constexpr int kRotCand[4][2] = {{1, 4}, {1, 5}, {3, 4}, {5, 4}};
+constexpr double kRotTuneMinWork = 8589934592.0;  // voxel-view updates per launch (2^33)
+constexpr double kRotSwitchRatio = 0.95;
+
+double rotation_cost(const fdk::GeoConst& gc, const fdk::ViewGeo& v, int32_t pitch, int32_t i_lo,
+                     int32_t j_lo, int32_t kb, int ra, int rb) {
+  double cost = 0.0;
+  int32_t base[64], rot[64];
+  double fvb[64], dvk[64];
+  for (int w = 0; w < 4; ++w) {
+    for (int l = 0; l < 64; ++l) {
+      const int tid = 64 * w + l, tx = tid % 16, ty = tid / 16;
+      const double i = std::min(i_lo + tx, gc.nx - 1), j = std::min(j_lo + ty, gc.ny - 1);
+      const double z = v.ci * i + v.cj * j + v.c0;
+      const double u = gc.cu + gc.ku * (v.ai * i + v.aj * j + v.a0) / z;
+      const double v0 = gc.cv + gc.kv * (kb - gc.cz) / z;
+      const double nvb = std::floor(v0);
+      base[l] = static_cast<int32_t>(std::floor(u)) * pitch + static_cast<int32_t>(nvb);
+      fvb[l] = v0 - nvb;
+      dvk[l] = gc.kv / z;
+      rot[l] = (ra * tx + rb * (ty & 3)) & 15;
+    }
+    for (int t = 0; t < 16; ++t) {
+      int32_t addr[64];
+      for (int l = 0; l < 64; ++l)
+        addr[l] = base[l] + static_cast<int32_t>(std::floor(fvb[l] + ((t + rot[l]) & 15) * dvk[l]));
+      const int32_t offs[4] = {0, pitch, 1, pitch + 1};  // the four taps of a splat
+      for (int32_t off : offs) {
+        int hist[64] = {0}, mx = 0;
+        for (int l = 0; l < 64; ++l) mx = std::max(mx, ++hist[(addr[l] + off) & 63]);
+        cost += mx;
+      }
+    }
+  }
+  return cost;
+}
+
+// Picks ts->rot_a, rot_b for one adjoint launch (FDK_FP_ROT=a,b forces a
+// choice: a tuning aid).
+void choose_rotation(const fdk::GeoConst& gc, const fdk::SliceRun& r, const fdk::ViewBatch& vb,
+                     int32_t bz, fdk::TileShape* ts) {
+  if (const char* env = std::getenv("FDK_FP_ROT")) {
+    int a = 1, b = 4;
+    if (std::sscanf(env, "%d,%d", &a, &b) == 2) {
+      ts->rot_a = a;
+      ts->rot_b = b;
+    }
+    return;
+  }
+  if (ts->vc <= 0 || vb.nviews <= 0) return;  // the direct variant adds to global memory
+  if (static_cast<double>(gc.nx) * gc.ny * r.n * vb.nviews < kRotTuneMinWork) return;
+  static const double kFrac[5][3] = {
+      {0.1, 0.15, 0.0}, {0.5, 0.5, 0.5}, {0.8, 0.25, 0.95}, {0.95, 0.95, 0.06}, {0.3, 0.7, 0.3}};
+  const int32_t views[3] = {0, vb.nviews / 2, vb.nviews - 1};
+  double cost0 = 0.0, best = 0.0;
+  int bi = 0;
+  for (int c = 0; c < 4; ++c) {
+    double cost = 0.0;
+    for (int32_t s : views) {
+      for (const auto& f : kFrac) {
+        const int32_t bx = static_cast<int32_t>(f[0] * (ts->nbx - 1));
+        const int32_t by = static_cast<int32_t>(f[1] * (ts->nby - 1));
+        const int32_t seg = static_cast<int32_t>(f[2] * (ts->nseg - 1));
+        cost += rotation_cost(gc, vb.view[s], ts->tvp, bx * fdk::kBrickX, by * fdk::kBrickY,
+                              r.k_first + seg * bz, kRotCand[c][0], kRotCand[c][1]);
+      }
+    }
+    if (c == 0) cost0 = cost;
+    if (c == 0 || cost < best) {
+      best = cost;
+      bi = c;
+    }
+  }
+  // The model ranks close candidates unreliably: leave the default unless
+  // another is clearly better.
+  if (best > kRotSwitchRatio * cost0) bi = 0;
+  ts->rot_a = kRotCand[bi][0];
+  ts->rot_b = kRotCand[bi][1];
 }
 
 struct Slab {
@@ -287,11 +377,12 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
     for (const fdk::SliceRun& r : sl.runs) {
       // Plain runs: 32-slice bricks and a single accumulation plane; their
       // flush has no prefetch budget to respect.
-      const fdk::TileShape ts =
+      fdk::TileShape ts =
           r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
                                      fdk::kPrefetchSlots)
                    : fdk::tile_shape(g, gc, r, vb, fdk::kPlainBrickZ, fdk::kPlainEntryBytes,
                                      std::numeric_limits<int32_t>::max());
+      choose_rotation(gc, r, vb, r.mirror ? fdk::kBrickZ : fdk::kPlainBrickZ, &ts);
       if (int e = fdk::launch_forward_project(gc, r, vb, ts, vol, q + (size_t)b * vstride,
                                               vstride, scale, stream))
         return fail(FDK_ERR_HIP, "forward-projection launch failed: HIP error %d", e);

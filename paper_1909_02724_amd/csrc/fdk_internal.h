@@ -68,6 +68,9 @@ struct TileShape {
   int32_t vc;            // views staged at once; 0 selects the direct variant
   int32_t rstep, rows;   // staging: rows advanced per pass, passes per view
   int32_t nbx, nby, nseg;  // bricks along x, y and z-segments of the run
+  // Adjoint: lane (tx, ty) visits its slots from (rot_a tx + rot_b (ty mod 4))
+  // mod 16 on, which spreads the lanes' LDS adds over the banks.
+  int32_t rot_a, rot_b;
 };
 
 // Kernel choice for a run and view batch: tiled unless the footprint tile

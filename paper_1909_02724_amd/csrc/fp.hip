@@ -40,9 +40,10 @@ __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_
 // address in the same instruction, which serialises; rotating each lane's
 // walk over its 16 slots by (tx + 4 ty) mod 16 puts such lanes on
 // different rows.
-__device__ __forceinline__ uint32_t slot_rotation() {
+__device__ __forceinline__ uint32_t slot_rotation(const TileShape& ts) {
   const uint32_t tx = threadIdx.x % kBrickX, ty = (threadIdx.x / kBrickX) & 3u;
-  return (tx + 4u * ty) & (kBrickZ - 1);
+  return (static_cast<uint32_t>(ts.rot_a) * tx + static_cast<uint32_t>(ts.rot_b) * ty) &
+         (kBrickZ - 1);
 }
 
 // Voxel values of the thread's column, scaled, in the lane's slot order:
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   if (tid >= v_lo && tid < v_hi)
     bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
                            MIRROR);
-  const uint32_t rot = slot_rotation();
+  const uint32_t rot = slot_rotation(ts);
   float x[kBrickZ], xm[kBrickZ];
   load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
   float amax = 0.0f;
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
   if (tid < vb.nviews)
     bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
                            MIRROR);
-  const uint32_t rot = slot_rotation();
+  const uint32_t rot = slot_rotation(ts);
   float x[kBrickZ], xm[kBrickZ];
   load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
   __syncthreads();
