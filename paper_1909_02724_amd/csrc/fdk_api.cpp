@@ -132,7 +132,7 @@ fdk::ViewGeo make_view(const fdk_geometry* g, double beta) {
 // summed over sample bricks and views. A uniform shift of all addresses
 // leaves that count unchanged, so tile origins are not needed.
 constexpr int kRotCand[4][2] = {{1, 4}, {1, 5}, {3, 4}, {5, 4}};
-constexpr double kRotTuneMinWork = 8589934592.0;  // voxel-view updates per launch (2^33)
+constexpr double kRotTuneMinWork = 2147483648.0;  // voxel-view updates per launch (2^31)
 constexpr double kRotSwitchRatio = 0.95;
 
 double rotation_cost(const fdk::GeoConst& gc, const fdk::ViewGeo& v, int32_t pitch, int32_t i_lo,
