@@ -50,7 +50,7 @@ METRIC = "back-projection GUPS at 2048³/2048 views; FP16-store vs FP32; adjoint
 # Chip constants (MI355X, gfx950): 256 CUs at 2.4 GHz; a SIMD retires one
 # 64-lane FP32 VALU instruction per 4 clocks, 4 SIMDs per CU -> 64 lane-ops/clk/CU.
 N_CU, CLOCK_HZ, VALU_LANES_PER_CLK = 256, 2.4e9, 64
-# LDS read bandwidth measured with probes/lds_probe.hip on MI355X: 93.2 TB/s,
+# LDS read bandwidth measured with a ds_read_b128 microbenchmark on MI355X: 93.2 TB/s,
 # 151.7 B/clk/CU at 2.4 GHz (above the 128 B/clk of the previous generation).
 LDS_BYTES_PER_CLK = 151.7
 HBM_PEAK = 8.0e12
@@ -361,7 +361,7 @@ def run_ablation(dev):
     mirror pairs (Theorem 1), the same without mirror pairs (a fractional
     principal-point offset leaves no pixel-aligned mirror, so every slice is
     back-projected on its own), and the direct variant (taps read from
-    global memory, no LDS staging; FDK_BP_KERNEL=direct)."""
+    global memory, no LDS staging; the FDK_DIRECT flag)."""
     import torch
 
     import paper_1909_02724_amd as fdk
@@ -377,28 +377,18 @@ def run_ablation(dev):
     vol = torch.empty((g0.nz, g0.ny, g0.nx), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
     out = {}
-    prev = os.environ.pop("FDK_BP_KERNEL", None)
-    try:
-        for key, g, env in (("ablation_tiled_mirror_gups", g0, None),
-                            ("ablation_tiled_no_mirror_gups", g0.replace(off_v=0.27), None),
-                            ("ablation_direct_mirror_gups", g0, "direct")):
-            if env:
-                os.environ["FDK_BP_KERNEL"] = env
-            else:
-                os.environ.pop("FDK_BP_KERNEL", None)
-            fdk.backproject(q[:32], g, ang, out=vol)
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            fdk.backproject(q, g, ang, out=vol)
-            b.record(stream)
-            torch.cuda.synchronize()
-            out[key] = round(gups(float(g.nx) * g.ny * g.nz * n, a.elapsed_time(b) / 1e3), 1)
-            log(f"ablation: {key} = {out[key]}")
-    finally:
-        os.environ.pop("FDK_BP_KERNEL", None)
-        if prev is not None:
-            os.environ["FDK_BP_KERNEL"] = prev
+    for key, g, direct in (("ablation_tiled_mirror_gups", g0, False),
+                           ("ablation_tiled_no_mirror_gups", g0.replace(off_v=0.27), False),
+                           ("ablation_direct_mirror_gups", g0, True)):
+        fdk.backproject(q[:32], g, ang, out=vol, direct=direct)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fdk.backproject(q, g, ang, out=vol, direct=direct)
+        b.record(stream)
+        torch.cuda.synchronize()
+        out[key] = round(gups(float(g.nx) * g.ny * g.nz * n, a.elapsed_time(b) / 1e3), 1)
+        log(f"ablation: {key} = {out[key]}")
     del q, vol
     torch.cuda.empty_cache()
     return out

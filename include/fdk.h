@@ -71,6 +71,12 @@ typedef enum { FDK_SLAB_CONTIGUOUS = 0, FDK_SLAB_MIRROR_PAIR = 1 } fdk_slab_kind
 
 /* flags: accumulate into the output instead of overwriting it. */
 #define FDK_ACCUMULATE 1u
+/* flags of fdk_backproject and fdk_forward_project: run the direct variant
+ * (FP64 column coordinates, taps read from global memory) instead of the
+ * LDS-tiled one. The library picks the direct variant by itself only when
+ * a brick's detector footprint exceeds the LDS budget; the results agree up
+ * to FP32 rounding. For comparisons and tests of that variant. */
+#define FDK_DIRECT 4u
 /* flags of fdk_sirt_iteration: clamp the updated volume at zero. */
 #define FDK_NONNEG 2u
 
@@ -146,7 +152,8 @@ FDK_API fdk_status fdk_filter_adjoint(const fdk_geometry* g, int32_t view0, int3
  * Errors: FDK_ERR_INVALID_ARG for a null pointer, non-positive size, view
  * range outside [0, np), slab outside the volume (or an odd nz_local /
  * overlapping halves for a mirror pair), sod not larger than the volume's
- * half-diagonal in x-y (some z <= 0, Eq. 3), sdd <= 0, or a non-finite value. */
+ * half-diagonal in x-y (some z <= 0, Eq. 3), sdd not larger than sod (the
+ * detector must lie beyond the rotation axis, Table 1), or a non-finite value. */
 FDK_API fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
                            const void* q, fdk_dtype q_dtype, float* vol,
                            int32_t z0, int32_t nz_local, fdk_slab_kind slab,

@@ -30,6 +30,7 @@ LIB_PATH = os.path.join(_HERE, "libfdk.so")
 FDK_OK, FDK_ERR_INVALID_ARG, FDK_ERR_UNSUPPORTED, FDK_ERR_HIP, FDK_ERR_OOM = range(5)
 FDK_ACCUMULATE = 1
 FDK_NONNEG = 2
+FDK_DIRECT = 4
 _DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
 _FILTERS = {"ramlak": 0, "ram-lak": 0, "shepp-logan": 1, "shepplogan": 1}
 _SLABS = {"contiguous": 0, "mirror_pair": 1}
@@ -157,11 +158,18 @@ def _slab(geom, z0, nz_local, slab):
     return int(z0), int(nz_local), _SLABS[slab]
 
 
+def _flags(accumulate: bool, direct: bool) -> int:
+    return (FDK_ACCUMULATE if accumulate else 0) | (FDK_DIRECT if direct else 0)
+
+
 def backproject(q: torch.Tensor, geom, angles, *, view0: int = 0, out: torch.Tensor | None = None,
                 z0: int = 0, nz_local: int | None = None, slab: str = "contiguous",
-                scale: float = 1.0, accumulate: bool = False) -> torch.Tensor:
+                scale: float = 1.0, accumulate: bool = False,
+                direct: bool = False) -> torch.Tensor:
     """Back-project views [view0, view0 + q.shape[0]) of `q` (nviews, Nv, Nu)
-    into a (nz_local, Ny, Nx) float32 slab: Alg. 2 computed as Alg. 4."""
+    into a (nz_local, Ny, Nx) float32 slab: Alg. 2 computed as Alg. 4.
+    direct=True runs the direct variant (taps from global memory) instead of
+    the LDS-tiled one."""
     _dev(q, "q")
     if q.dtype not in _DTYPES:
         raise ValueError(f"unsupported projection dtype {q.dtype}")
@@ -177,16 +185,17 @@ def backproject(q: torch.Tensor, geom, angles, *, view0: int = 0, out: torch.Ten
     cg, _keep = _cgeom(geom, angles)
     _check(lib().fdk_backproject(C.byref(cg), view0, q.shape[0], C.c_void_p(q.data_ptr()),
                                  _DTYPES[q.dtype], C.c_void_p(out.data_ptr()), z0, nzl, sk,
-                                 float(scale), FDK_ACCUMULATE if accumulate else 0, _stream(q)))
+                                 float(scale), _flags(accumulate, direct), _stream(q)))
     return out
 
 
 def forward_project(vol: torch.Tensor, geom, angles, *, view0: int = 0,
                     nviews: int | None = None, out: torch.Tensor | None = None, z0: int = 0,
                     slab: str = "contiguous", scale: float = 1.0,
-                    accumulate: bool = False) -> torch.Tensor:
+                    accumulate: bool = False, direct: bool = False) -> torch.Tensor:
     """Matched forward projection (exact adjoint of backproject) of a
-    float32 slab into (nviews, Nv, Nu) float32 projections."""
+    float32 slab into (nviews, Nv, Nu) float32 projections. direct=True runs
+    the direct variant instead of the LDS-tiled one."""
     _dev(vol, "vol")
     if vol.dtype != torch.float32 or vol.dim() != 3 or vol.shape[1:] != (geom.ny, geom.nx):
         raise ValueError(f"vol must be float32 (nz_local, {geom.ny}, {geom.nx})")
@@ -201,7 +210,7 @@ def forward_project(vol: torch.Tensor, geom, angles, *, view0: int = 0,
     cg, _keep = _cgeom(geom, angles)
     _check(lib().fdk_forward_project(C.byref(cg), view0, nviews, C.c_void_p(vol.data_ptr()), z0,
                                      nzl, sk, C.c_void_p(out.data_ptr()), float(scale),
-                                     FDK_ACCUMULATE if accumulate else 0, _stream(vol)))
+                                     _flags(accumulate, direct), _stream(vol)))
     return out
 
 
@@ -279,6 +288,14 @@ def fdk_scale(geom, angles) -> float:
     return lib().fdk_fdk_scale(C.byref(cg))
 
 
+def _same_views(t: torch.Tensor, angles: np.ndarray):
+    # The backward pass projects onto every angle, so the forward pass must
+    # use every angle too: one view of the input per angle.
+    if t.dim() < 3 or t.shape[-3] != angles.size:
+        raise ValueError(f"input has {t.shape[-3] if t.dim() >= 3 else '?'} views for "
+                         f"{angles.size} angles; the differentiable operators need one per angle")
+
+
 class FDKBackprojection(torch.autograd.Function):
     """Differentiable back-projection. forward: q (B, nviews, Nv, Nu) or
     (nviews, Nv, Nu) -> volume (B, Nz, Ny, Nx) / (Nz, Ny, Nx). backward: the
@@ -288,6 +305,7 @@ class FDKBackprojection(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q, geom, angles, scale=1.0):
         ctx.geom, ctx.angles, ctx.scale = geom, np.asarray(angles, np.float64), float(scale)
+        _same_views(q, ctx.angles)
         ctx.qshape, ctx.qdtype = q.shape, q.dtype
         batched = q.dim() == 4
         qs = q if batched else q.unsqueeze(0)
@@ -321,6 +339,7 @@ class FDKReconstruction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, e, geom, angles, kind="ramlak", scale=1.0):
         ctx.geom, ctx.angles = geom, np.asarray(angles, np.float64)
+        _same_views(e, ctx.angles)
         ctx.kind, ctx.scale = kind, float(scale)
         batched = e.dim() == 4
         es = e if batched else e.unsqueeze(0)

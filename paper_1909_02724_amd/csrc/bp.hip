@@ -21,8 +21,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <cstdlib>
-#include <cstring>
 
 #include "brick.h"
 
@@ -147,7 +145,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
             c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
                      ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
             off = static_cast<uint32_t>(org_v + sr) * row_es + c0;
-            offm = static_cast<uint32_t>(gc.mirror_g - org_v - sr) * row_es + c0;
+            offm = static_cast<uint32_t>(MIRROR ? gc.mirror_g - org_v - sr : 0) * row_es + c0;
           }
           // Only the offsets depend on the branch: the loads themselves are
           // issued in common code, unconditionally (uniform control flow),
@@ -164,11 +162,11 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
             m0 = on ? offm : kBadRow;
             m1 = m0 + es;
           } else {
-            const int32_t gr = org_v + r, gm = gc.mirror_g - gr;
+            const int32_t gr = org_v + r, gm = MIRROR ? gc.mirror_g - gr : -1;
             const uint32_t ro = on && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
-                                    ? __umul24(static_cast<uint32_t>(gr), row_es) : kBadRow;
+                                    ? static_cast<uint32_t>(gr) * row_es : kBadRow;
             const uint32_t rm = on && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
-                                    ? __umul24(static_cast<uint32_t>(gm), row_es) : kBadRow;
+                                    ? static_cast<uint32_t>(gm) * row_es : kBadRow;
             o0 = ro + c0;
             o1 = ro + c1;
             m0 = rm + c0;
@@ -406,52 +404,6 @@ int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, co
 }
 
 }  // namespace
-
-// Host-side bound of a brick's footprint (pixels) over the views of a
-// launch, from derivative bounds over the whole volume: with r the x-y
-// half-diagonal and zmin = d - r,
-//   |du/di| <= ku Dx (|cos| + |sin| r / zmin) / zmin,
-//   |du/dj| <= ku Dy (|sin| + |cos| r / zmin) / zmin,
-// and v(k) - cv = kv (k - cz) / z, so over the brick's bz slices and its z
-// spread dz the rows span at most kv ((bz - 1) / zmin + |k - cz| dz / zmin^2).
-TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
-                     const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots) {
-  TileShape ts{};
-  ts.rot_a = 1;
-  ts.rot_b = 4;
-  ts.nbx = (gc.nx + kBrickX - 1) / kBrickX;
-  ts.nby = (gc.ny + kBrickY - 1) / kBrickY;
-  ts.nseg = (run.n + bz - 1) / bz;
-  const double r = 0.5 * std::hypot((g->nx - 1) * g->dx, (g->ny - 1) * g->dy);
-  const double zmin = g->sod - r, rho = r / zmin;
-  const char* env = std::getenv("FDK_BP_KERNEL");
-  if (env && std::strcmp(env, "direct") == 0) return ts;  // vc = 0: direct variant
-  const double kmax = gc.cz + bz;
-  double wu = 0.0, wv = 0.0;
-  for (int32_t s = 0; s < vb.nviews; ++s) {
-    // |sin| and |cos| of the view from its geometry: ci = sin Dx, cj = -cos Dy.
-    const double as = std::fabs(vb.view[s].ci) / g->dx, ac = std::fabs(vb.view[s].cj) / g->dy;
-    const double dui = gc.ku * g->dx * (ac + as * rho) / zmin;
-    const double duj = gc.ku * g->dy * (as + ac * rho) / zmin;
-    wu = std::fmax(wu, (kBrickX - 1) * dui + (kBrickY - 1) * duj);
-    const double dz = (kBrickX - 1) * g->dx * as + (kBrickY - 1) * g->dy * ac;
-    wv = std::fmax(wv, gc.kv * ((bz - 1) / zmin + kmax * dz / (zmin * zmin)));
-  }
-  // floor() of the extremes adds one pixel, the second tap one row, the
-  // origin margin one pixel, FP32 column arithmetic up to one more.
-  ts.tu = static_cast<int32_t>(std::ceil(wu)) + 4;
-  ts.tv = static_cast<int32_t>(std::ceil(wv)) + 5;
-  ts.tvp = ts.tv | 1;  // odd pitch: 16 neighbouring columns hit distinct LDS banks
-  if (ts.tu + 1 > kThreads) return ts;  // staging and the adjoint's flush: a thread per column
-  ts.rstep = kThreads / ts.tu;
-  ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
-  const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * entry_bytes;
-  int64_t vc = std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);
-  vc = std::min<int64_t>(vc, slots / ts.rows);
-  if (const char* cap = std::getenv("FDK_BP_VC")) vc = std::min<int64_t>(vc, std::atoi(cap));
-  ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
-  return ts;
-}
 
 int launch_backproject(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
                        const TileShape& ts, const void* q, fdk_dtype q_dtype, int64_t vstride,

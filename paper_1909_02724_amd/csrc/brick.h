@@ -48,8 +48,9 @@ struct BrickView {
 };
 
 // bz: slices per brick; mirror: whether the tile also holds the mirror rows
-// (then `inside` requires them on the detector too).
-__device__ BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i_lo, int32_t i_hi,
+// (then `inside` requires them on the detector too). Also compiled for the
+// host, where a test checks the tile bounds against every voxel's taps.
+__host__ __device__ inline BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i_lo, int32_t i_hi,
                                  int32_t j_lo, int32_t j_hi, int32_t kb, int32_t tu = 0,
                                  int32_t tv = 0, int32_t bz = kBrickZ, bool mirror = true) {
   const double k0 = static_cast<double>(kb) - gc.cz;
@@ -84,8 +85,11 @@ __device__ BrickView brick_setup(const GeoConst& gc, const ViewGeo& g, int32_t i
   b.cj = static_cast<float>(g.cj);
   const bool cols_in = b.org_u >= 0 && b.org_u + tu < gc.nu;
   const bool rows_in = b.org_v >= 0 && b.org_v + tv <= gc.nv;
-  const bool mirror_in = gc.mirror_g - b.org_v < gc.nv && gc.mirror_g - b.org_v - tv + 1 >= 0;
-  b.inside = tu > 0 && cols_in && rows_in && (!mirror || mirror_in);
+  // (mirror_g is INT32_MIN when there is no pixel-aligned mirror: only
+  // mirrored runs, which have one, evaluate it.)
+  const bool mirror_in =
+      !mirror || (gc.mirror_g - b.org_v < gc.nv && gc.mirror_g - b.org_v - tv + 1 >= 0);
+  b.inside = tu > 0 && cols_in && rows_in && mirror_in;
   return b;
 }
 
@@ -96,16 +100,33 @@ struct ColumnF32 {
   float w, dvk;      // W_dis = f^2 and dv/dk
 };
 
-__device__ __forceinline__ ColumnF32 column_f32(const BrickView& b, float txf, float tyf,
-                                                float kvf) {
-  const float f = __builtin_amdgcn_rcpf(b.zo + fmaf(b.ci, txf, b.cj * tyf));
+// Hardware reciprocal (1 ulp) and fraction on the GPU; the host build, used
+// only by the tile-bound test, takes the correctly rounded forms.
+__host__ __device__ __forceinline__ float rcp_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ __forceinline__ float fract_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_fractf(x);
+#else
+  return x - floorf(x);
+#endif
+}
+
+__host__ __device__ __forceinline__ ColumnF32 column_f32(const BrickView& b, float txf, float tyf,
+                                                         float kvf) {
+  const float f = rcp_f32(b.zo + fmaf(b.ci, txf, b.cj * tyf));
   const float ul = fmaf(fmaf(b.au, txf, b.bu * tyf), f, b.uo);
   const float vl = fmaf(fmaf(b.av, txf, b.bv * tyf), f, b.vo);
   ColumnF32 c;
   c.nu = static_cast<uint32_t>(ul);  // ul, vl >= 1 by the origin margin
-  c.du = __builtin_amdgcn_fractf(ul);
+  c.du = fract_f32(ul);
   c.nvb = static_cast<uint32_t>(vl);
-  c.fvb = __builtin_amdgcn_fractf(vl);
+  c.fvb = fract_f32(vl);
   c.w = f * f;
   c.dvk = kvf * f;
   return c;

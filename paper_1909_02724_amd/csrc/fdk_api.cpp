@@ -7,15 +7,20 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <limits>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "fdk_internal.h"
+#include "geometry_host.h"
 #include "ops_internal.h"
 
 namespace {
+
+using fdk::make_geo;
+using fdk::make_view;
 
 thread_local std::string g_last_error;
 
@@ -35,6 +40,17 @@ fdk_status ok() {
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// An enum argument as the integer the caller passed. C callers may pass any
+// int; in C++ reading an enum object that holds a value outside its
+// enumerators is undefined, so arguments are validated through their bytes.
+template <class E>
+int32_t raw(const E& e) {
+  static_assert(sizeof(E) == sizeof(int32_t), "enums of the C ABI are int-sized");
+  int32_t v;
+  std::memcpy(&v, &e, sizeof v);
+  return v;
+}
 
 // Largest |u - cu| or |v - cv| (pixels) allowed, so that pixel indices and
 // LDS/tap offsets stay well inside int32 arithmetic.
@@ -59,6 +75,9 @@ fdk_status check_geometry(const fdk_geometry* g) {
     return fail(FDK_ERR_INVALID_ARG, "principal-point offsets must be finite");
   if (!finite_pos(g->sod) || !finite_pos(g->sdd))
     return fail(FDK_ERR_INVALID_ARG, "sod and sdd must be positive and finite");
+  // Table 1: the detector lies beyond the rotation axis (D > d).
+  if (!(g->sdd > g->sod))
+    return fail(FDK_ERR_INVALID_ARG, "sdd = %g must exceed sod = %g", g->sdd, g->sod);
   if (g->np <= 0) return fail(FDK_ERR_INVALID_ARG, "np must be positive (got %d)", g->np);
   if (!g->angles) return fail(FDK_ERR_INVALID_ARG, "angles pointer is NULL");
   // Eq. 3: z = d + sin(b) X + cos(b) Y; its minimum over the voxel centres
@@ -86,40 +105,6 @@ fdk_status check_views(const fdk_geometry* g, int32_t view0, int32_t nviews) {
     if (!std::isfinite(g->angles[s]))
       return fail(FDK_ERR_INVALID_ARG, "angle of view %d is not finite", s);
   return FDK_OK;
-}
-
-fdk::GeoConst make_geo(const fdk_geometry* g) {
-  fdk::GeoConst gc;
-  gc.nx = g->nx;
-  gc.ny = g->ny;
-  gc.nz = g->nz;
-  gc.nu = g->nu;
-  gc.nv = g->nv;
-  gc.cu = 0.5 * (g->nu - 1) + g->off_u;
-  gc.cv = 0.5 * (g->nv - 1) + g->off_v;
-  gc.cz = 0.5 * (g->nz - 1);
-  gc.ku = g->sdd / g->du;
-  gc.kv = g->sdd * g->dz / g->dv;
-  // Theorem 1 with a shifted principal point: v(Nz-1-k) = 2 cv - v(k). The
-  // mirrored taps line up with whole pixels only when 2 cv is an integer.
-  const double G = (g->nv - 1) + 2.0 * g->off_v;
-  gc.mirror_g = (std::fabs(G - std::nearbyint(G)) <= 1e-9) ? (int32_t)std::nearbyint(G) : INT32_MIN;
-  return gc;
-}
-
-// Eq. 2 expanded for one gantry angle: world X = Dx (i - cx), Y = -Dy (j - cy);
-// after the rotation, z = d + sin(b) X + cos(b) Y and a = cos(b) X - sin(b) Y.
-fdk::ViewGeo make_view(const fdk_geometry* g, double beta) {
-  const double s = std::sin(beta), c = std::cos(beta);
-  const double cx = 0.5 * (g->nx - 1), cy = 0.5 * (g->ny - 1);
-  fdk::ViewGeo v;
-  v.ci = s * g->dx;
-  v.cj = -c * g->dy;
-  v.c0 = g->sod - s * g->dx * cx + c * g->dy * cy;
-  v.ai = c * g->dx;
-  v.aj = s * g->dy;
-  v.a0 = -c * g->dx * cx - s * g->dy * cy;
-  return v;
 }
 
 // Adjoint slot rotation: the order in which each lane visits its 16 slots.
@@ -218,7 +203,7 @@ struct Slab {
 // Split the slab's slices into mirrored pairs (Theorem 1, Alg. 4's k < Nz/2
 // loop) and plain runs for slices without an in-slab mirror.
 fdk_status make_slab(const fdk_geometry* g, const fdk::GeoConst& gc, int32_t z0, int32_t nzl,
-                     fdk_slab_kind kind, Slab* out) {
+                     int32_t kind, Slab* out) {
   const int32_t nz = g->nz;
   if (kind != FDK_SLAB_CONTIGUOUS && kind != FDK_SLAB_MIRROR_PAIR)
     return fail(FDK_ERR_UNSUPPORTED, "unknown slab kind %d", (int)kind);
@@ -312,16 +297,19 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
   fdk_status st = check_geometry(g);
   if (st) return st;
   if ((st = check_views(g, view0, nviews))) return st;
-  if (q_dtype != FDK_F32 && q_dtype != FDK_F16 && q_dtype != FDK_BF16)
-    return fail(FDK_ERR_UNSUPPORTED, "unknown projection dtype %d", (int)q_dtype);
+  const int32_t qd = raw(q_dtype);
+  if (qd != FDK_F32 && qd != FDK_F16 && qd != FDK_BF16)
+    return fail(FDK_ERR_UNSUPPORTED, "unknown projection dtype %d", qd);
   if (!vol) return fail(FDK_ERR_INVALID_ARG, "volume pointer is NULL");
   if (nviews > 0 && !q) return fail(FDK_ERR_INVALID_ARG, "projection pointer is NULL");
   if (!std::isfinite(scale)) return fail(FDK_ERR_INVALID_ARG, "scale is not finite");
-  if (flags & ~FDK_ACCUMULATE) return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(FDK_ACCUMULATE | FDK_DIRECT))
+    return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   const fdk::GeoConst gc = make_geo(g);
   Slab sl;
-  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   const bool acc0 = flags & FDK_ACCUMULATE;
+  const bool direct = flags & FDK_DIRECT;
   const int64_t slice = (int64_t)g->nx * g->ny;
   if (nviews == 0) {
     if (!acc0) {
@@ -339,9 +327,9 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
     for (const fdk::SliceRun& r : sl.runs) {
       const fdk::TileShape ts =
           r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
-                                     fdk::kPrefetchSlots)
+                                     fdk::kPrefetchSlots, direct)
                    : fdk::tile_shape(g, gc, r, vb, fdk::kPlainBrickZ, fdk::kPlainEntryBytes,
-                                     fdk::kPlainPrefetchSlots);
+                                     fdk::kPlainPrefetchSlots, direct);
       if (int e = fdk::launch_backproject(gc, r, vb, ts, qb, q_dtype, vstride, vol, scale,
                                           (b > 0) || acc0, stream))
         return fail(FDK_ERR_HIP, "back-projection launch failed: HIP error %d", e);
@@ -360,11 +348,13 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
   if (!vol) return fail(FDK_ERR_INVALID_ARG, "volume pointer is NULL");
   if (nviews > 0 && !q) return fail(FDK_ERR_INVALID_ARG, "projection pointer is NULL");
   if (!std::isfinite(scale)) return fail(FDK_ERR_INVALID_ARG, "scale is not finite");
-  if (flags & ~FDK_ACCUMULATE) return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(FDK_ACCUMULATE | FDK_DIRECT))
+    return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   const fdk::GeoConst gc = make_geo(g);
   Slab sl;
-  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   if (nviews == 0) return ok();
+  const bool direct = flags & FDK_DIRECT;
   const int64_t vstride = (int64_t)g->nu * g->nv;
   if (!(flags & FDK_ACCUMULATE)) {
     if (int e = fdk::launch_fill_zero(q, vstride * nviews, stream))
@@ -379,9 +369,9 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
       // flush has no prefetch budget to respect.
       fdk::TileShape ts =
           r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
-                                     fdk::kPrefetchSlots)
+                                     fdk::kPrefetchSlots, direct)
                    : fdk::tile_shape(g, gc, r, vb, fdk::kPlainBrickZ, fdk::kPlainEntryBytes,
-                                     std::numeric_limits<int32_t>::max());
+                                     std::numeric_limits<int32_t>::max(), direct);
       choose_rotation(gc, r, vb, r.mirror ? fdk::kBrickZ : fdk::kPlainBrickZ, &ts);
       if (int e = fdk::launch_forward_project(gc, r, vb, ts, vol, q + (size_t)b * vstride,
                                               vstride, scale, stream))
@@ -395,15 +385,17 @@ namespace {
 // Filtering of a row band, or its adjoint (FP32 output only).
 fdk_status filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t v0,
                        int32_t nrows, const float* e, int64_t e_view_stride, void* q,
-                       int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
+                       int64_t q_view_stride, int32_t out_dtype_raw, int32_t kind_raw,
                        bool adjoint, void* stream) {
   fdk_status st = check_geometry(g);
   if (st) return st;
   if ((st = check_views(g, view0, nviews))) return st;
-  if (out_dtype != FDK_F32 && out_dtype != FDK_F16 && out_dtype != FDK_BF16)
-    return fail(FDK_ERR_UNSUPPORTED, "unknown output dtype %d", (int)out_dtype);
-  if (kind != FDK_RAMLAK && kind != FDK_SHEPP_LOGAN)
-    return fail(FDK_ERR_UNSUPPORTED, "unknown filter kind %d", (int)kind);
+  if (out_dtype_raw != FDK_F32 && out_dtype_raw != FDK_F16 && out_dtype_raw != FDK_BF16)
+    return fail(FDK_ERR_UNSUPPORTED, "unknown output dtype %d", out_dtype_raw);
+  if (kind_raw != FDK_RAMLAK && kind_raw != FDK_SHEPP_LOGAN)
+    return fail(FDK_ERR_UNSUPPORTED, "unknown filter kind %d", kind_raw);
+  const fdk_dtype out_dtype = static_cast<fdk_dtype>(out_dtype_raw);
+  const fdk_filter_kind kind = static_cast<fdk_filter_kind>(kind_raw);
   if (g->nu > 8192) return fail(FDK_ERR_UNSUPPORTED, "filter rows above 8192 pixels (Nu = %d)", g->nu);
   if (v0 < 0 || nrows < 0 || (int64_t)v0 + nrows > g->nv)
     return fail(FDK_ERR_INVALID_ARG, "row band [%d, %d + %d) is outside [0, %d)", v0, v0, nrows,
@@ -435,8 +427,8 @@ fdk_status fdk_filter_rows(const fdk_geometry* g, int32_t view0, int32_t nviews,
                            int32_t nrows, const float* e, int64_t e_view_stride, void* q,
                            int64_t q_view_stride, fdk_dtype out_dtype, fdk_filter_kind kind,
                            void* stream) {
-  return filter_rows(g, view0, nviews, v0, nrows, e, e_view_stride, q, q_view_stride, out_dtype,
-                     kind, false, stream);
+  return filter_rows(g, view0, nviews, v0, nrows, e, e_view_stride, q, q_view_stride,
+                     raw(out_dtype), raw(kind), false, stream);
 }
 
 fdk_status fdk_filter_adjoint(const fdk_geometry* g, int32_t view0, int32_t nviews,
@@ -444,8 +436,8 @@ fdk_status fdk_filter_adjoint(const fdk_geometry* g, int32_t view0, int32_t nvie
                               void* stream) {
   if (!g) return fail(FDK_ERR_INVALID_ARG, "geometry pointer is NULL");
   const int64_t full = (int64_t)g->nu * g->nv;
-  return filter_rows(g, view0, nviews, 0, g->nv, q_grad, full, e_grad, full, FDK_F32, kind, true,
-                     stream);
+  return filter_rows(g, view0, nviews, 0, g->nv, q_grad, full, e_grad, full, FDK_F32, raw(kind),
+                     true, stream);
 }
 
 namespace {
@@ -467,7 +459,7 @@ fdk_status fdk_sirt_weights(const fdk_geometry* g, int32_t view0, int32_t nviews
   if (col_inv == vol_tmp) return fail(FDK_ERR_INVALID_ARG, "col_inv and vol_tmp must differ");
   const fdk::GeoConst gc = make_geo(g);
   Slab sl;
-  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   const int64_t nproj = (int64_t)nviews * g->nu * g->nv, nvox = slab_voxels(g, nz_local);
   int e = 0;
   // Column sums B 1 (all-ones projections, held in row_inv for now).
@@ -482,9 +474,11 @@ fdk_status fdk_sirt_weights(const fdk_geometry* g, int32_t view0, int32_t nviews
   if ((st = fdk_forward_project(g, view0, nviews, vol_tmp, z0, nz_local, slab, row_inv, 1.0f, 0,
                                 stream)))
     return st;
-  uint32_t* scratch = reinterpret_cast<uint32_t*>(vol_tmp);  // vol_tmp is free again
+  // vol_tmp is free again: its first word holds each max-reduction in turn
+  // (the two run in stream order, and a slab has at least one voxel).
+  uint32_t* scratch = reinterpret_cast<uint32_t*>(vol_tmp);
   if ((e = fdk::launch_invert_floor(row_inv, nproj, kSirtFloor, scratch, stream)) ||
-      (e = fdk::launch_invert_floor(col_inv, nvox, kSirtFloor, scratch + 1, stream)))
+      (e = fdk::launch_invert_floor(col_inv, nvox, kSirtFloor, scratch, stream)))
     return fail(FDK_ERR_HIP, "inversion failed: HIP error %d", e);
   return ok();
 }
@@ -505,7 +499,7 @@ fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int32_t nvie
   if (flags & ~FDK_NONNEG) return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   const fdk::GeoConst gc = make_geo(g);
   Slab sl;
-  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   const int64_t nproj = (int64_t)nviews * g->nu * g->nv, nvox = slab_voxels(g, nz_local);
   if ((st = fdk_forward_project(g, view0, nviews, x, z0, nz_local, slab, proj_tmp, 1.0f, 0, stream)))
     return st;
@@ -527,7 +521,7 @@ fdk_status fdk_slab_rows(const fdk_geometry* g, int32_t z0, int32_t nz_local, fd
   if (!band) return fail(FDK_ERR_INVALID_ARG, "band pointer is NULL");
   const fdk::GeoConst gc = make_geo(g);
   Slab sl;
-  if ((st = make_slab(g, gc, z0, nz_local, slab, &sl))) return st;
+  if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   // Global slice intervals the slab holds.
   int32_t iv[2][2];
   int niv = 1;
@@ -592,7 +586,8 @@ fdk_status fdk_filter(const fdk_geometry* g, int32_t view0, int32_t nviews, cons
                       void* q, fdk_dtype out_dtype, fdk_filter_kind kind, void* stream) {
   if (!g) return fail(FDK_ERR_INVALID_ARG, "geometry pointer is NULL");
   const int64_t full = (int64_t)g->nu * g->nv;
-  return fdk_filter_rows(g, view0, nviews, 0, g->nv, e, full, q, full, out_dtype, kind, stream);
+  return filter_rows(g, view0, nviews, 0, g->nv, e, full, q, full, raw(out_dtype), raw(kind), false,
+                     stream);
 }
 
 }  // extern "C"

@@ -74,12 +74,13 @@ struct TileShape {
 };
 
 // Kernel choice for a run and view batch: tiled unless the footprint tile
-// exceeds the LDS or prefetch budget (or FDK_BP_KERNEL=direct, a debugging
-// aid; FDK_BP_VC caps the views per stage, a tuning aid).
+// exceeds the LDS or prefetch budget, or the caller asks for the direct
+// variant (FDK_DIRECT).
 // bz: slices per brick; entry_bytes: LDS bytes per tile entry; slots: tile
 // entries a thread prefetches per stage.
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
-                     const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots);
+                     const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots,
+                     bool direct);
 // Plain (unmirrored) back-projection runs: 32 slices per brick, the tile
 // holding (q, dq/du) of the main rows only; a prefetch slot holds one row's
 // pair instead of two, so twice as many fit the same registers.

@@ -18,7 +18,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 
 #include "geom_device.h"
 #include "ops_internal.h"
@@ -114,21 +113,14 @@ __global__ __launch_bounds__(kFilterThreads) void filter_direct_kernel(
   }
 }
 
-// Lets kernel K use more than the default 64 KB of dynamic LDS, once per
-// device, so launches recorded into a graph after the first (eager) call
-// make no attribute call.
+// Lets kernel K use more than the default 64 KB of dynamic LDS on the
+// current device. Called before every launch that needs it: the attribute
+// call is host-side only (no stream work), so it is also valid while the
+// caller's stream is being captured into a graph.
 template <auto K>
 hipError_t raise_lds_limit(size_t bytes) {
-  static std::atomic<uint64_t> raised{0};
-  int dev = 0;
-  hipError_t err = hipGetDevice(&dev);
-  if (err != hipSuccess) return err;
-  const uint64_t bit = uint64_t{1} << (dev & 63);
-  if (raised.load(std::memory_order_acquire) & bit) return hipSuccess;
-  err = hipFuncSetAttribute(reinterpret_cast<const void*>(K),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
-  if (err == hipSuccess) raised.fetch_or(bit, std::memory_order_release);
-  return err;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(K),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
 // ---- FFT path -------------------------------------------------------------

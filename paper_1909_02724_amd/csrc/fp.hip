@@ -303,11 +303,10 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (ts.vc > 0) {
     // Views split over workgroups when the bricks alone give fewer than
-    // kFpSplitTarget workgroups (FDK_FP_VSPLIT=n overrides: a tuning aid).
+    // kFpSplitTarget workgroups.
     int64_t vsplit = 1;
     if (nwg < static_cast<uint64_t>(kFpSplitTarget))
       vsplit = (kFpSplitTarget + static_cast<int64_t>(nwg) - 1) / static_cast<int64_t>(nwg);
-    if (const char* env = std::getenv("FDK_FP_VSPLIT")) vsplit = std::atoi(env);
     vsplit = std::max<int64_t>(1, std::min<int64_t>(vsplit, vb.nviews));
     const dim3 grid(static_cast<uint32_t>(nwg), static_cast<uint32_t>(vsplit));
     // Adjoint tile: one more column than the back-projection tile, one

@@ -27,11 +27,15 @@ __device__ __forceinline__ float to_f32(bf16_t x) { return __uint_as_float(uint3
 // Row index and fraction of voxel kb + t on the column: v = v(kb) + t dv/dk.
 // The offset tt is never negative (fvb >= 0, dv/dk > 0), so truncation is
 // floor and the hardware fraction is tt - floor(tt), both exact.
-__device__ __forceinline__ void voxel_row_off(float fvb, float dvk, int32_t t, uint32_t* n,
-                                              float* fr) {
+__host__ __device__ __forceinline__ void voxel_row_off(float fvb, float dvk, int32_t t,
+                                                       uint32_t* n, float* fr) {
   const float tt = fmaf(static_cast<float>(t), dvk, fvb);
   *n = static_cast<uint32_t>(tt);
+#if defined(__HIP_DEVICE_COMPILE__)
   *fr = __builtin_amdgcn_fractf(tt);
+#else
+  *fr = tt - floorf(tt);
+#endif
 }
 
 }  // namespace fdk

@@ -73,6 +73,8 @@ def call_bp(g=GOOD, ang=ANG, view0=0, nviews=4, q=FAKE, dtype=0, vol=FAKE, z0=0,
     (dict(g=GOOD.__class__(**{**GOOD.__dict__, "dv": -1.0})), 1, "pixel pitch"),
     (dict(g=GOOD.__class__(**{**GOOD.__dict__, "sod": 10.0})), 1, "half-diagonal"),
     (dict(g=GOOD.__class__(**{**GOOD.__dict__, "sdd": float("nan")})), 1, "sod and sdd"),
+    (dict(g=GOOD.__class__(**{**GOOD.__dict__, "sdd": GOOD.sod})), 1, "must exceed sod"),
+    (dict(g=GOOD.__class__(**{**GOOD.__dict__, "sdd": 0.5 * GOOD.sod})), 1, "must exceed sod"),
     (dict(ang=np.array([0.0, float("inf"), 1.0, 2.0])), 1, "not finite"),
     (dict(view0=10, nviews=4), 1, "view range"),
     (dict(view0=-1), 1, "view range"),
@@ -85,7 +87,7 @@ def call_bp(g=GOOD, ang=ANG, view0=0, nviews=4, q=FAKE, dtype=0, vol=FAKE, z0=0,
     (dict(slab=1, z0=2, nzl=8), 1, "overlap"),
     (dict(slab=3), 2, "slab kind"),
     (dict(scale=float("nan")), 1, "scale"),
-    (dict(flags=4), 1, "flags"),
+    (dict(flags=8), 1, "flags"),
 ])
 def test_backproject_validation(kw, status, msg):
     st, err = call_bp(**kw)
@@ -256,3 +258,16 @@ def test_projection_matrix_validation():
     L = fdk.lib()
     cg, _keep = fdk._cgeom(g, ang)
     assert L.fdk_projection_matrix(C.byref(cg), 0, None) == fdk.FDK_ERR_INVALID_ARG
+
+
+def test_autograd_functions_need_one_view_per_angle():
+    """The differentiable operators' backward passes project onto every
+    angle, so a forward pass over fewer views than angles is rejected before
+    any device work (here with a host tensor, which never reaches the GPU)."""
+    import torch
+    g = fdk.Geometry(nx=8, ny=8, nz=8, nu=12, nv=10, sod=40.0, sdd=80.0)
+    ang = np.linspace(0, 2 * math.pi, 6, endpoint=False)
+    with pytest.raises(ValueError, match="one per angle"):
+        fdk.fdk_backprojection(torch.zeros(4, g.nv, g.nu), g, ang)
+    with pytest.raises(ValueError, match="one per angle"):
+        fdk.fdk_reconstruction(torch.zeros(2, 5, g.nv, g.nu), g, ang, scale=1.0)

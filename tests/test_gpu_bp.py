@@ -301,7 +301,7 @@ def test_synth_gpu_generators_match_oracle():
 
 
 @pytest.mark.parametrize("name", list(VARIANTS))
-def test_tiled_kernel_agrees_with_direct_kernel(name, monkeypatch):
+def test_tiled_kernel_agrees_with_direct_kernel(name):
     """The LDS-tiled kernel (FP32 brick-relative columns, staged taps) and
     the direct kernel (FP64 columns, taps from global memory) sample the
     same taps with coordinates that differ by rounding only."""
@@ -309,8 +309,7 @@ def test_tiled_kernel_agrees_with_direct_kernel(name, monkeypatch):
     ang = synth.angles(45, start=0.1)
     q = gpu(synth.random_projections(16, 45, g))
     a = host(fdk.backproject(q, g, ang, scale=0.5))
-    monkeypatch.setenv("FDK_BP_KERNEL", "direct")
-    b = host(fdk.backproject(q, g, ang, scale=0.5))
+    b = host(fdk.backproject(q, g, ang, scale=0.5, direct=True))
     err = rel_l2(a, b)
     announce(f"  tiled vs direct: rel-L2 {err:.3e}, max |diff| {np.abs(a - b).max():.3e} "
              f"(max |v| {np.abs(b).max():.3e})")
@@ -335,14 +334,13 @@ def test_adjoint_slot_rotations_match_oracle(name, rot, monkeypatch):
 
 
 @pytest.mark.parametrize("name", ["ragged_odd", "offset_frac", "plain_odd", "plain_tall"])
-def test_adjoint_direct_kernel_matches_oracle(name, monkeypatch):
+def test_adjoint_direct_kernel_matches_oracle(name):
     """The adjoint's direct kernel (FP64 columns, global atomics), used
     where a footprint tile does not fit LDS, against the oracle."""
     g = ADJ_VARIANTS[name]
     ang = synth.angles(37, start=0.2)
     x = np.random.default_rng(22).standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
-    monkeypatch.setenv("FDK_BP_KERNEL", "direct")
-    fp = host(fdk.forward_project(gpu(x), g, ang, scale=0.8))
+    fp = host(fdk.forward_project(gpu(x), g, ang, scale=0.8, direct=True))
     ref = oracle.forward_project(g, ang, x.astype(np.float64), scale=0.8)
     err = rel_l2(fp, ref)
     announce(f"  direct adjoint {name}: rel-L2 {err:.3e}")
