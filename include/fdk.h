@@ -221,6 +221,24 @@ FDK_API fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int3
                                       float lambda, uint32_t flags, float* proj_tmp,
                                       float* vol_tmp, void* stream);
 
+/* One MLEM iteration (maximum-likelihood expectation maximisation, Shepp
+ * and Vardi 1982; another of the iterative methods the paper names as users
+ * of the back-projection) on x (device FP32 slab, updated in place) for
+ * measured projections p (device FP32 (nviews, Nv, Nu)), with the same
+ * matched pair, views and slab as fdk_sirt_iteration:
+ *     x <- x * C * B(p / max(F x, 1e-3 max(F x))),
+ * and a ratio of 0 where that denominator is 0. C is col_inv from
+ * fdk_sirt_weights (the inverse column sums 1 / B 1, raised as there).
+ * MLEM's domain is non-negative: x and p must hold no negative values (not
+ * checked); a positive start (e.g. all ones) stays positive where the
+ * volume is seen. proj_tmp (projection-sized) and vol_tmp (slab-sized) are
+ * device workspaces whose contents are overwritten; neither may alias an
+ * input. Errors: as fdk_sirt_iteration. */
+FDK_API fdk_status fdk_mlem_iteration(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                                      const float* p, const float* col_inv, float* x, int32_t z0,
+                                      int32_t nz_local, fdk_slab_kind slab, float* proj_tmp,
+                                      float* vol_tmp, void* stream);
+
 /* The 3 x 4 projection matrix P_s of Eq. 2 that every kernel uses for view
  * `view` (angle g->angles[view]), in the reduced form of Eq. 3 and
  * Theorems 2-3: for voxel (i, j, k), [x, y, z] = P [i, j, k, 1] with z the

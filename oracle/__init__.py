@@ -18,6 +18,7 @@ Each wrapped routine names the passage of Chen et al. (SC'19) it follows:
   filter_rows         Alg. 1 on a list of detector rows
   filter_adjoint      the transpose of Alg. 1
   sirt                SIRT (Gilbert 1972) with forward_project / backproject
+  mlem                MLEM (Shepp and Vardi 1982) with the same pair
   phantom_project     analytic line integrals of an ellipsoid phantom
 """
 from __future__ import annotations
@@ -341,3 +342,24 @@ def sirt(geom, angles, p, n_iter, lam=1.0, nonneg=False, x0=None):
         if nonneg:
             x = np.maximum(x, 0.0)
     return x
+
+
+MLEM_FLOOR = 1e-3  # ratio denominators below this fraction of the largest are raised to it
+
+
+def mlem(geom, angles, p, n_iter, x0=None):
+    """MLEM (Shepp and Vardi 1982): x <- x C B(p / F x), FP64, full volume,
+    with C the inverse column sums of sirt_weights (1 / B 1, raised like
+    there) and each ratio's denominator raised to at least MLEM_FLOOR of the
+    largest F x of that iteration (rays that barely touch the support would
+    otherwise divide by next to nothing). Starts from x0, default ones."""
+    _, Cw = sirt_weights(geom, angles)
+    x = np.ones((geom.nz, geom.ny, geom.nx)) if x0 is None else _f64(x0).copy()
+    pf = _f64(p)
+    for _ in range(n_iter):
+        fx = forward_project(geom, angles, x)
+        den = np.maximum(fx, MLEM_FLOOR * fx.max())
+        ratio = np.divide(pf, den, out=np.zeros_like(pf), where=den > 0)  # 0 where F x is 0
+        x = x * Cw * backproject(geom, angles, ratio)
+    return x
+

@@ -22,6 +22,7 @@ __all__ = [
     "Geometry", "FDKError", "lib", "backproject", "forward_project", "filter",
     "filter_adjoint", "slab_rows", "fdk_scale", "FDKBackprojection", "fdk_backprojection",
     "FDKReconstruction", "fdk_reconstruction", "sirt_weights", "sirt_iteration", "sirt",
+    "mlem_iteration", "mlem",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -115,6 +116,10 @@ def lib():
                                          C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int,
                                          C.c_float, C.c_uint32, C.c_void_p, C.c_void_p,
                                          C.c_void_p]
+        L.fdk_mlem_iteration.restype = C.c_int
+        L.fdk_mlem_iteration.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_int32, C.c_int32, C.c_int, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]
         L.fdk_slab_rows.restype = C.c_int
         L.fdk_slab_rows.argtypes = [P, C.c_int32, C.c_int32, C.c_int, C.POINTER(C.c_int32)]
         L.fdk_fdk_scale.restype = C.c_double
@@ -421,4 +426,36 @@ def sirt(p, geom, angles, n_iter: int, *, lam: float = 1.0, nonneg: bool = False
     for _ in range(n_iter):
         sirt_iteration(x, p, row_inv, col_inv, geom, angles, z0=z0, slab=slab, lam=lam,
                        nonneg=nonneg, proj_tmp=proj_tmp, vol_tmp=vol_tmp)
+    return x
+
+
+def mlem_iteration(x, p, col_inv, geom, angles, *, view0: int = 0, z0: int = 0,
+                   slab: str = "contiguous", proj_tmp=None, vol_tmp=None):
+    """One MLEM update of x (non-negative slab, in place) towards
+    non-negative projections p; col_inv from sirt_weights."""
+    z0, nzl, sk = _slab(geom, z0, x.shape[0], slab)
+    _f32_dev(x, (nzl, geom.ny, geom.nx), "x")
+    _f32_dev(p, (p.shape[0], geom.nv, geom.nu), "p")
+    _f32_dev(col_inv, x.shape, "col_inv")
+    proj_tmp = torch.empty_like(p) if proj_tmp is None else proj_tmp
+    vol_tmp = torch.empty_like(x) if vol_tmp is None else vol_tmp
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_mlem_iteration(C.byref(cg), view0, p.shape[0], C.c_void_p(p.data_ptr()),
+                                    C.c_void_p(col_inv.data_ptr()), C.c_void_p(x.data_ptr()), z0,
+                                    nzl, sk, C.c_void_p(proj_tmp.data_ptr()),
+                                    C.c_void_p(vol_tmp.data_ptr()), _stream(x)))
+    return x
+
+
+def mlem(p, geom, angles, n_iter: int, *, x0=None, z0: int = 0, nz_local: int | None = None,
+         slab: str = "contiguous"):
+    """n_iter MLEM iterations from x0 (default all ones) for non-negative
+    projections p (nviews, Nv, Nu) float32 of views [0, nviews)."""
+    _, col_inv = sirt_weights(geom, angles, nviews=p.shape[0], z0=z0, nz_local=nz_local,
+                              slab=slab, device=p.device)
+    x = torch.ones_like(col_inv) if x0 is None else x0.clone()
+    proj_tmp, vol_tmp = torch.empty_like(p), torch.empty_like(x)
+    for _ in range(n_iter):
+        mlem_iteration(x, p, col_inv, geom, angles, z0=z0, slab=slab, proj_tmp=proj_tmp,
+                       vol_tmp=vol_tmp)
     return x

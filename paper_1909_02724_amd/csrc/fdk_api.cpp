@@ -446,6 +446,7 @@ int64_t slab_voxels(const fdk_geometry* g, int32_t nz_local) {
   return (int64_t)nz_local * g->ny * g->nx;
 }
 constexpr float kSirtFloor = 1e-3f;  // sums below this fraction of the largest one are raised to it
+constexpr float kMlemFloor = 1e-3f;  // ratio denominators below this fraction of the largest are raised
 }  // namespace
 
 fdk_status fdk_sirt_weights(const fdk_geometry* g, int32_t view0, int32_t nviews, int32_t z0,
@@ -511,6 +512,36 @@ fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int32_t nvie
   e = fdk::launch_sirt_update(x, col_inv, vol_tmp, nvox, lambda, (flags & FDK_NONNEG) ? 1 : 0,
                               stream);
   if (e) return fail(FDK_ERR_HIP, "update failed: HIP error %d", e);
+  return ok();
+}
+
+fdk_status fdk_mlem_iteration(const fdk_geometry* g, int32_t view0, int32_t nviews, const float* p,
+                              const float* col_inv, float* x, int32_t z0, int32_t nz_local,
+                              fdk_slab_kind slab, float* proj_tmp, float* vol_tmp, void* stream) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if ((st = check_views(g, view0, nviews))) return st;
+  if (nviews <= 0) return fail(FDK_ERR_INVALID_ARG, "MLEM needs at least one view");
+  if (!p || !col_inv || !x || !proj_tmp || !vol_tmp)
+    return fail(FDK_ERR_INVALID_ARG, "MLEM buffer pointer is NULL");
+  if (proj_tmp == p || vol_tmp == x || vol_tmp == col_inv)
+    return fail(FDK_ERR_INVALID_ARG, "MLEM workspaces must not alias the inputs");
+  const fdk::GeoConst gc = make_geo(g);
+  Slab sl;
+  if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
+  const int64_t nproj = (int64_t)nviews * g->nu * g->nv, nvox = slab_voxels(g, nz_local);
+  if ((st = fdk_forward_project(g, view0, nviews, x, z0, nz_local, slab, proj_tmp, 1.0f, 0, stream)))
+    return st;
+  // The ratio's max-reduction word lives in vol_tmp, which the
+  // back-projection overwrites only afterwards (stream order).
+  int e = fdk::launch_mlem_ratio(p, proj_tmp, nproj, kMlemFloor,
+                                 reinterpret_cast<uint32_t*>(vol_tmp), stream);
+  if (e) return fail(FDK_ERR_HIP, "MLEM ratio failed: HIP error %d", e);
+  if ((st = fdk_backproject(g, view0, nviews, proj_tmp, FDK_F32, vol_tmp, z0, nz_local, slab, 1.0f,
+                            0, stream)))
+    return st;
+  e = fdk::launch_mlem_update(x, col_inv, vol_tmp, nvox, stream);
+  if (e) return fail(FDK_ERR_HIP, "MLEM update failed: HIP error %d", e);
   return ok();
 }
 

@@ -17,6 +17,12 @@ int launch_invert_floor(float* p, int64_t n, float floor_rel, uint32_t* maxbits,
 int launch_sirt_residual(const float* p, const float* row_inv, float* r, int64_t n, void* stream);
 int launch_sirt_update(float* x, const float* col_inv, const float* b, int64_t n, float lambda,
                        int nonneg, void* stream);
+// MLEM: r <- p / max(r, floor_rel * max(r)) (0 where that is 0), r holding
+// F x on entry (non-negative); maxbits: one device word of scratch.
+int launch_mlem_ratio(const float* p, float* r, int64_t n, float floor_rel, uint32_t* maxbits,
+                      void* stream);
+// MLEM: x <- x * col_inv * b.
+int launch_mlem_update(float* x, const float* col_inv, const float* b, int64_t n, void* stream);
 // Filter rows [v0, v0 + band) of nviews views; row m of the launch is view
 // m / band, detector row v0 + m % band; view strides in elements.
 struct RowBand {

@@ -1,7 +1,8 @@
-// Element-wise kernels of the SIRT iteration built on the matched pair
-// (back-projection B and its transpose F): the inverse row and column sums
-// of F and the fused residual and update steps. Memory-bound grid-stride
-// loops over contiguous FP32 arrays.
+// Element-wise kernels of the iterative methods built on the matched pair
+// (back-projection B and its transpose F): SIRT's inverse row and column
+// sums of F and its fused residual and update steps, and MLEM's guarded
+// ratio and multiplicative update. Memory-bound grid-stride loops over
+// contiguous FP32 arrays.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,6 +66,26 @@ __global__ void update_kernel(float* __restrict__ x, const float* __restrict__ c
   }
 }
 
+// MLEM ratio: r <- p / max(r, floor_rel * max(r)), and 0 where that
+// denominator is 0; r holds F x on entry.
+__global__ void mlem_ratio_kernel(const float* __restrict__ p, float* __restrict__ r, int64_t n,
+                                  const uint32_t* __restrict__ maxbits, float floor_rel) {
+  const float lo = floor_rel * __uint_as_float(*maxbits);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; m < n; m += stride) {
+    const float den = fmaxf(r[m], lo);
+    r[m] = den > 0.0f ? p[m] / den : 0.0f;
+  }
+}
+
+// MLEM update: x <- x * col_inv * b.
+__global__ void mlem_update_kernel(float* __restrict__ x, const float* __restrict__ col_inv,
+                                   const float* __restrict__ b, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t m = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; m < n; m += stride)
+    x[m] = x[m] * (col_inv[m] * b[m]);
+}
+
 dim3 ew_grid(int64_t n) {
   return dim3(static_cast<uint32_t>(std::min<int64_t>((n + kEwThreads - 1) / kEwThreads, kEwMaxBlocks)));
 }
@@ -100,6 +121,25 @@ int launch_sirt_update(float* x, const float* col_inv, const float* b, int64_t n
   if (n <= 0) return 0;
   hipLaunchKernelGGL(update_kernel, ew_grid(n), dim3(kEwThreads), 0,
                      static_cast<hipStream_t>(stream), x, col_inv, b, n, lambda, nonneg);
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_mlem_ratio(const float* p, float* r, int64_t n, float floor_rel, uint32_t* maxbits,
+                      void* stream) {
+  if (n <= 0) return 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(kEwThreads), 0, st,
+                     reinterpret_cast<float*>(maxbits), int64_t{1}, 0.0f);
+  hipLaunchKernelGGL(max_kernel, ew_grid(n), dim3(kEwThreads), 0, st, r, n, maxbits);
+  hipLaunchKernelGGL(mlem_ratio_kernel, ew_grid(n), dim3(kEwThreads), 0, st, p, r, n, maxbits,
+                     floor_rel);
+  return static_cast<int>(hipGetLastError());
+}
+
+int launch_mlem_update(float* x, const float* col_inv, const float* b, int64_t n, void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(mlem_update_kernel, ew_grid(n), dim3(kEwThreads), 0,
+                     static_cast<hipStream_t>(stream), x, col_inv, b, n);
   return static_cast<int>(hipGetLastError());
 }
 

@@ -226,6 +226,22 @@ def test_sirt_validation():
     assert "flags" in L.fdk_last_error().decode()
 
 
+def test_mlem_validation():
+    L = fdk.lib()
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    A, B_, X, E_, F_ = (C.c_void_p(0x1000 * k) for k in (1, 2, 3, 5, 6))
+    it = L.fdk_mlem_iteration
+    assert it(C.byref(cg), 0, 4, None, B_, X, 0, 8, 0, E_, F_, None) == 1
+    assert "NULL" in L.fdk_last_error().decode()
+    assert it(C.byref(cg), 0, 4, A, B_, X, 0, 8, 0, A, F_, None) == 1      # proj_tmp is p
+    assert "alias" in L.fdk_last_error().decode()
+    assert it(C.byref(cg), 0, 4, A, B_, X, 0, 8, 0, E_, X, None) == 1      # vol_tmp is x
+    assert it(C.byref(cg), 0, 4, A, B_, X, 0, 8, 0, E_, B_, None) == 1     # vol_tmp is col_inv
+    assert it(C.byref(cg), 0, 0, A, B_, X, 0, 8, 0, E_, F_, None) == 1     # no views
+    assert it(C.byref(cg), 0, 4, A, B_, X, 4, 8, 0, E_, F_, None) == 1     # slab past Nz
+    assert it(C.byref(cg), 0, 4, A, B_, X, 0, 8, 5, E_, F_, None) == 2     # unknown slab kind
+
+
 @pytest.mark.parametrize("gi", [0, 1, 2])
 def test_projection_matrix_matches_oracle(orc, gi):
     """The host geometry the kernels are built from (fdk_projection_matrix,

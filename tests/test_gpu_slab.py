@@ -145,6 +145,28 @@ def test_streamed_slab_matches_oracle(slab, z0, nzl, dtype):
     assert err <= (1e-5 if dtype == torch.float32 else 2e-3)
 
 
+def c4_clusters(g, ks, seed, n_clusters=8, side=8, depth=8):
+    """n_clusters blocks of side x side columns x depth consecutive slab
+    slices (inside one half of the mirror pair), at seeded places that
+    include both ends of each half: n_clusters * side^2 * depth voxels whose
+    taps need only a few hundred detector rows per view, so the oracle can
+    recompute every row they read."""
+    rng = np.random.default_rng(seed)
+    half = ks.size // 2
+    starts = [0, half - depth, half, ks.size - depth]
+    starts += list(rng.integers(0, half - depth, (n_clusters - 4) // 2))
+    starts += list(half + rng.integers(0, half - depth, n_clusters - len(starts)))
+    out = []
+    for c, t0 in enumerate(starts):
+        i0 = int(rng.integers(0, g.nx - side)) if c % 3 else 0   # some at the volume's edge
+        j0 = int(rng.integers(0, g.ny - side))
+        for t in range(depth):
+            for j in range(j0, j0 + side):
+                for i in range(i0, i0 + side):
+                    out.append((i, j, ks[t0 + t]))
+    return np.ascontiguousarray(np.array(out, dtype=np.int64))
+
+
 def c4_voxels(g, ks, seed, n):
     rng = np.random.default_rng(seed)
     i = rng.integers(0, g.nx, n)
@@ -174,7 +196,8 @@ def test_slab4096_streamed_pipeline_sampled():
                            slab=sl["kind"], chunk=c["B"], dtype=torch.float16,
                            kind=c["filter"], scale=scale, chunks=chunks, device=DEV)
     ks = slab_slices(g, sl["z0"], sl["nz_local"], sl["kind"])
-    vox = c4_voxels(g, ks, 205, 40)
+    vox = c4_clusters(g, ks, 205)
+    announce(f"slab4096: {len(vox)} sampled voxels in 8 clusters")
     loc = np.searchsorted(ks, vox[:, 2])
     idx = torch.from_numpy(np.stack([loc, vox[:, 1], vox[:, 0]])).to(DEV)
     got = vol[idx[0], idx[1], idx[2]].double().cpu().numpy()
