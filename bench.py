@@ -54,33 +54,42 @@ N_CU, CLOCK_HZ, VALU_LANES_PER_CLK = 256, 2.4e9, 64
 # 151.7 B/clk/CU at 2.4 GHz (above the 128 B/clk of the previous generation).
 LDS_BYTES_PER_CLK = 151.7
 HBM_PEAK = 8.0e12
-# VALU work per voxel-view update of the mirrored, difference-staged scheme:
-# per voxel pair v, truncation, fraction and tap address (4, shared); per
-# voxel two u-interpolations (1 FMA each on the staged difference), one
-# v-interpolation (2) and the weighted accumulate (1): (4 + 2 * 5) / 2 = 7.
-VALU_OPS_PER_UPDATE = 7.0
-LDS_BYTES_PER_UPDATE = 16.0  # 4 FP32 taps (value and u-difference of two rows)
+# VALU work per voxel-view update of the mirrored, cell-staged scheme: per
+# voxel pair v, truncation, fraction and cell address (4, shared); per voxel
+# the cell's bilinear form q + du q_u + fr (q_v + du q_uv) (3 FMAs) and the
+# weighted accumulate (1): (4 + 2 * 4) / 2 = 6.
+VALU_OPS_PER_UPDATE = 6.0
+LDS_BYTES_PER_UPDATE = 16.0  # one 16-byte cell (q, q_u, q_v, q_uv) per voxel
+# The adjoint's scheme: per voxel W x (1), the row split (2) and the four tap
+# weights (4); per voxel pair v, truncation and fraction (3, shared); the
+# adds themselves are LDS atomics: 7 + 1.5 = 8.5 VALU ops and four 4-byte
+# LDS read-modify-writes per update.
+ADJ_VALU_OPS_PER_UPDATE = 8.5
+ADJ_LDS_BYTES_PER_UPDATE = 32.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "bp_tiled_mirror_kernel_bp2048_traffic.json")
 # Slab workload: views are filtered in 16-view chunks; two contiguous chunks
 # make one back-projection launch (the volume is read and written per launch).
 SLAB_VIEWS_PER_LAUNCH = 32
 
 
-def profiled_traffic(workload):
-    """HBM bytes per launch of the back-projection kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by the calibration copy),
-    or None if the kernel sources changed since they were taken."""
+def profiled_counters(workload):
+    """The committed rocprofv3 record of the back-projection kernel at
+    2048^3: HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE passes
+    (scaled by the calibration copy) and VALU instructions per launch, or
+    None (each) if the kernel sources changed since they were taken."""
     import hashlib
     if workload != "bp2048" or not os.path.exists(TRAFFIC_RECORD):
-        return None
+        return None, None
     rec = json.load(open(TRAFFIC_RECORD))
     h = hashlib.sha256()
     for f in rec["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest()[:16] != rec["sources_sha256_16"]:
-        return None
-    return (rec["fetch_size_kib_per_dispatch"] * rec["copy_read_factor"] +
-            rec["write_size_kib_per_dispatch"] * rec["copy_write_factor"]) * 1024.0
+        return None, None
+    traffic = (rec["fetch_size_kib_per_dispatch"] * rec["copy_read_factor"] +
+               rec["write_size_kib_per_dispatch"] * rec["copy_write_factor"]) * 1024.0
+    valu = rec.get("sq_insts_valu_per_dispatch")
+    return traffic, valu
 
 
 def gups(updates: float, seconds: float) -> float:
@@ -416,27 +425,49 @@ def oracle_configs(oracle, threads):
     return out
 
 
-def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic):
+def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic,
+                valu_insts=None, valu_ops=VALU_OPS_PER_UPDATE, lds_bytes=LDS_BYTES_PER_UPDATE):
+    """The kernel against its roofs: VALU issue at the scheme's minimal op
+    count per update, LDS bandwidth at its bytes per update (the measured
+    ds_read peak), HBM at the algorithmic bytes (the volume read and written
+    once per launch, each view read once). `peak` is the lower of the VALU
+    and LDS roofs; `bound` stays "alu" (on-chip work, not HBM or MFMA) and
+    `binding_roof` names which of the two sets the peak."""
     per_launch_s = ms_step / 1e3 / launches
     updates_per_launch = updates / launches
     achieved = gups(updates_per_launch, per_launch_s)
-    valu_roof = N_CU * VALU_LANES_PER_CLK * CLOCK_HZ / VALU_OPS_PER_UPDATE / 2 ** 30
-    lds_roof = N_CU * LDS_BYTES_PER_CLK * CLOCK_HZ / LDS_BYTES_PER_UPDATE / 2 ** 30
+    valu_rate = N_CU * VALU_LANES_PER_CLK * CLOCK_HZ  # lane-ops per second
+    valu_roof = valu_rate / valu_ops / 2 ** 30
+    lds_roof = N_CU * LDS_BYTES_PER_CLK * CLOCK_HZ / lds_bytes / 2 ** 30
     peak = min(valu_roof, lds_roof)
     nz = updates / (float(g.nx) * g.ny * views_per_launch * launches)
-    return {
+    alg_bytes = updates_per_launch * (8.0 / views_per_launch +
+                                      g.nu * g.nv * q_bytes / (g.nx * g.ny * nz))
+    out = {
         "bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1), "unit": "GUPS",
         "frac": round(achieved / peak, 4),
         "traffic": None if traffic is None else round(traffic),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
         "kernel": kernel, "launches_per_step": launches,
         "avg_launch_ms": round(per_launch_s * 1e3, 3),
-        "valu_roof_gups": round(valu_roof, 1), "lds_roof_gups": round(lds_roof, 1),
+        "binding_roof": "lds" if lds_roof < valu_roof else "valu",
+        "valu_roof_gups": round(valu_roof, 1), "valu_ops_per_update_scheme": valu_ops,
+        "valu_frac": round(achieved / valu_roof, 4),
+        "lds_roof_gups": round(lds_roof, 1), "lds_bytes_per_update": lds_bytes,
+        "lds_frac": round(achieved / lds_roof, 4),
+        "hbm_algorithmic_bytes_per_launch": round(alg_bytes),
+        "hbm_frac_algorithmic": round(alg_bytes / per_launch_s / HBM_PEAK, 4),
         "hbm_achieved_GBps": None if traffic is None else round(traffic / per_launch_s / 1e9, 1),
         "hbm_peak_GBps": HBM_PEAK / 1e9,
-        "hbm_algorithmic_bytes_per_launch": round(updates_per_launch * (
-            8.0 / views_per_launch + g.nu * g.nv * q_bytes / (g.nx * g.ny * nz))),
+        "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_bytes, 3),
     }
+    if valu_insts is not None:
+        # Measured lane-ops per update (rocprofv3 SQ_INSTS_VALU x 64 lanes) and
+        # the VALU issue rate they imply at the achieved speed.
+        ops = valu_insts * 64.0 / updates_per_launch
+        out["valu_lane_ops_per_update_measured"] = round(ops, 3)
+        out["valu_issue_frac_measured"] = round(achieved * 2 ** 30 * ops / valu_rate, 4)
+    return out
 
 
 def main_slab(args):
@@ -541,20 +572,61 @@ def main():
         step_ms[label] = ms
         return sum(ms) / len(ms)
 
+    # Accuracy of each storage leg against the FP64 oracle: the same kernel
+    # and launch shape on a subset of the views (8 launches of 32 consecutive
+    # views at starting angles spread over the circle), sampled voxels.
+    n_acc = min(256, n_views)
+    acc_views = np.concatenate([np.arange(s0, s0 + 32) for s0 in
+                                np.linspace(0, n_views - 32, n_acc // 32).astype(int)])
+    acc_ang = np.ascontiguousarray(ang[acc_views])
+    acc_vox = synth.sample_voxels(211, g, 16384, columns=4)
+    acc_idx = torch.from_numpy(acc_vox).to(dev)
+    acc_got = {}
+
+    def sample_subset(q, label):
+        qs = q[torch.from_numpy(acc_views).to(dev)]
+        fdk.backproject(qs, g, acc_ang, out=vol, scale=scale)
+        acc_got[label] = vol[acc_idx[:, 2], acc_idx[:, 1], acc_idx[:, 0]].double().cpu().numpy()
+        del qs
+
     # ---- FP32 storage: the headline figure ----
     ms32 = timed_bp(q32, args.steps, args.warmup, "fp32")
     gups32 = gups(updates, ms32 / 1e3)
     log(f"fp32: {gups32:.1f} GUPS")
     result_extra = {}
+    if not args.no_cpu_baseline:
+        sample_subset(q32, "fp32")
 
     if not args.no_16bit:
         for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
             q16 = q32.to(dt)
-            ms16 = timed_bp(q16, max(1, args.steps // 2), 1, name)
+            ms16 = timed_bp(q16, max(3, args.steps // 2), 1, name)
             result_extra[f"{name}_store_gups"] = round(gups(updates, ms16 / 1e3), 2)
             result_extra[f"{name}_ms_per_step"] = round(ms16, 2)
+            result_extra[f"{name}_roofline"] = {
+                k: v for k, v in roofline_of(ms16, launches, updates, g, 32, 2.0,
+                                             f"bp_tiled_mirror_kernel<{name}_t>", None).items()
+                if k not in ("traffic", "traffic_unit", "hbm_achieved_GBps",
+                             "traffic_over_algorithmic")}
+            if not args.no_cpu_baseline:
+                sample_subset(q16, name)
             del q16
             torch.cuda.empty_cache()
+
+    if acc_got:
+        import oracle
+        t_acc = time.time()
+        ref = oracle.backproject(g, acc_ang, q32[torch.from_numpy(acc_views).to(dev)].cpu()
+                                 .numpy().astype(np.float64), scale=scale, voxels=acc_vox)
+        for label, got in acc_got.items():
+            err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            result_extra[f"{label}_rel_l2_vs_oracle"] = float(f"{err:.3e}")
+            log(f"{label}: rel-L2 {err:.3e} against the FP64 oracle (FP32 inputs), "
+                f"{len(acc_vox)} sampled voxels x {n_acc} views")
+        result_extra["rel_l2_sample"] = (f"{len(acc_vox)} voxels (seed 211, 4 full z-columns) x "
+                                         f"{n_acc} views (8 launches of 32 spread over the "
+                                         f"circle), oracle fed the FP32 projections")
+        log(f"oracle comparison in {time.time() - t_acc:.1f} s")
 
     if not args.no_adjoint:
         nv_adj = min(args.adjoint_views, n_views)
@@ -565,21 +637,34 @@ def main():
         qa = torch.empty((nv_adj, g.nv, g.nu), dtype=torch.float32, device=dev)
         fdk.forward_project(x, g, ang_adj, nviews=nv_adj, out=qa, scale=scale)
         torch.cuda.synchronize()
-        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ea.record(stream)
-        fdk.forward_project(x, g, ang_adj, nviews=nv_adj, out=qa, scale=scale)
-        eb.record(stream)
+        reps = 5
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for k in range(reps):
+            fdk.forward_project(x, g, ang_adj, nviews=nv_adj, out=qa, scale=scale)
+            ev[k + 1].record(stream)
         torch.cuda.synchronize()
-        msa = ea.elapsed_time(eb)
-        result_extra["adjoint_gups"] = round(gups(float(g.nx) * g.ny * g.nz * nv_adj, msa / 1e3), 2)
+        msl = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+        msa = float(np.median(msl))
+        ua = float(g.nx) * g.ny * g.nz * nv_adj
+        result_extra["adjoint_gups"] = round(gups(ua, msa / 1e3), 2)
+        result_extra["adjoint_gups_mean"] = round(gups(ua, float(np.mean(msl)) / 1e3), 2)
         result_extra["adjoint_views_timed"] = nv_adj
-        log(f"adjoint: {result_extra['adjoint_gups']} GUPS over {nv_adj} views spread over the "
-            f"circle ({msa:.1f} ms)")
+        result_extra["adjoint_reps"] = reps
+        result_extra["adjoint_roofline"] = {
+            k: v for k, v in roofline_of(msa, math.ceil(nv_adj / 32), ua, g, 32, 4.0,
+                                         "fp_tiled_kernel<true>", None,
+                                         valu_ops=ADJ_VALU_OPS_PER_UPDATE,
+                                         lds_bytes=ADJ_LDS_BYTES_PER_UPDATE).items()
+            if not (k.startswith("hbm") or k.startswith("traffic"))}
+        log(f"adjoint: {result_extra['adjoint_gups']} GUPS (median of {reps}) over {nv_adj} "
+            f"views spread over the circle (ms {['%.1f' % m for m in msl]})")
         del x, qa
 
     # ---- roofline of the dominant kernel (the back-projection launches) ----
+    traffic, valu_insts = profiled_counters(args.workload)
     roofline = roofline_of(ms32, launches, updates, g, 32, 4.0, "bp_tiled_mirror_kernel<float>",
-                           profiled_traffic(args.workload))
+                           traffic, valu_insts)
 
     if not args.no_sirt and args.workload == "bp2048":
         result_extra.update(run_sirt(dev))

@@ -7,14 +7,13 @@
 // Short rows (and rows too long for the FFT tile) use a direct convolution:
 // one workgroup per row, the weighted row and the kernel taps in LDS.
 //
-// Longer rows use the convolution theorem (Sec. 2.2.3): rows are
-// zero-padded to L >= 2 Nu - 1 (a power of two), so the circular
-// convolution of length L equals the linear one on the Nu outputs. Two rows
-// travel as the real and imaginary parts of one complex sequence: the ramp
-// kernel is real and even, its spectrum H is real, and IFFT(FFT(a + i b) H) =
-// (a * h) + i (b * h). The FFTs are radix-16 Stockham passes over points held
-// in registers, exchanged through LDS between passes; each workgroup computes
-// H once and then loops over row pairs.
+// Longer rows use the convolution theorem (Sec. 2.2.3) on the row's first
+// difference and the running sum of the kernel (an identity by summation by
+// parts, detailed at the FFT path below), in FP32 transforms of a
+// power-of-two length L >= 2 Nu, so the circular convolution equals the
+// linear one on the Nu outputs. Two rows travel as the real and imaginary
+// parts of one complex sequence. The FFTs are radix-16 Stockham passes over
+// points held in registers, exchanged through LDS between passes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -124,24 +123,35 @@ hipError_t raise_lds_limit(size_t bytes) {
 }
 
 // ---- FFT path -------------------------------------------------------------
-// Stockham FFT of L = 2^LOGL points in FP64: every thread holds 16 points in
-// registers; a pass gathers R points strided by L/R, applies the twiddles
-// W^(r k), runs an R-point DFT in registers and scatters the results to their
-// autosorted places, through one padded LDS buffer per FFT. Passes are radix
-// 16, plus one first pass of radix 2, 4 or 8 when LOGL is not a multiple of
-// four (that pass needs no twiddles). The forward transform's first pass
-// reads the rows from global memory, the inverse transform's last pass writes
-// them, so a row pair crosses LDS 2 P - 1 times for P passes.
+// Ramp filtering as a first difference followed by a convolution with the
+// running sum of the kernel. With g(m) = sum of tau h(j) over -N < j <= m,
+// for m in [-N, N) (so g(-N) = 0 and g(m) - g(m - 1) = tau h(m) on the
+// kernel's support |m| < N), summation by parts gives, for a in [0, N),
+//   q(a) = sum_{n < N} g(a - n) y(n) - c g(a - N),
+// with y(n) = x(n) - x(n - 1) (x(-1) = 0) the first difference of the
+// weighted row x and c = x(N - 1) its last value. This is the factorisation
+// of the ramp into a derivative and a Hilbert-type transform: |w| over
+// |1 - e^{-iw}| stays within a factor of about pi/2 of its mean, so g's
+// spectrum G is nearly flat. That is what allows FP32 transforms. The ramp
+// removes most of a smooth row's content: transformed directly, the FP32
+// rounding of its large low-frequency terms spreads over all bins, which
+// the ramp then amplifies (1e-6 to 2e-5 rel-L2 off the FP64 result on
+// projections of ellipsoid phantoms, 512 to 4096 pixels). y carries only
+// the row's variation and G weights every bin about equally, so FP32
+// transforms of y stay within a few FP32 roundings of the output (about
+// 1e-7). y is formed in FP64 from the FP32 row and FP64 weights and rounded
+// once; g comes from an FP64 scan.
 //
-// Why FP64: the ramp filter removes most of a smooth row's content (its low
-// frequencies), so FP32 rounding in the transform, relative to the input's
-// size, is large relative to the output. On projections of ellipsoid
-// phantoms an FP32 transform misses the FP64 result by 1e-5 (512-pixel rows)
-// to 7e-5 (4096-pixel rows) rel-L2; in FP64 the output is the FP64 result
-// rounded. FP64 FMAs issue at the FP32 (non-packed) rate on this GPU; the
-// cost is LDS bytes and registers.
-using cx = double2;
-__device__ __forceinline__ cx make_cx(double x, double y) { return make_double2(x, y); }
+// Rows are zero-padded to a power of two L >= 2N: with y supported on
+// [0, N) and g on [-N, N), the circular convolution of length L equals the
+// linear one on the N outputs. Two rows travel as the real and imaginary
+// parts of one complex sequence: g is real, so
+// IFFT(FFT(a + i b) G) = (g * a) + i (g * b). The FFTs are radix-16 Stockham
+// passes over points held in registers, exchanged through LDS between
+// passes; the inverse transform is the forward one of the conjugate. Each
+// workgroup computes G and the correction's g(a - N) once and then loops
+// over row pairs.
+using cf = float2;
 
 template <int LOGL>
 struct FftCfg {
@@ -169,34 +179,34 @@ struct PassCfg {
 // conflicts.
 __device__ __forceinline__ int32_t fpad(int32_t i) { return i + (i >> 4); }
 
-__device__ __forceinline__ cx cmul(cx a, cx b) {
-  return make_cx(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+__device__ __forceinline__ cf cmul(cf a, cf b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 
 // x W16^q with W16 = exp(-2 pi i / 16), q in [0, 8): exact rotations by
 // multiples of pi/2 and pi/4 use adds only.
-__device__ __forceinline__ cx rot16(cx x, int q) {
-  constexpr double c1 = 0.92387953251128675613;  // cos(pi/8)
-  constexpr double s1 = 0.38268343236508977173;  // sin(pi/8)
-  constexpr double h = 0.70710678118654752440;   // sqrt(1/2)
+__device__ __forceinline__ cf rot16(cf x, int q) {
+  constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+  constexpr float h = 0.70710678118654752440f;   // sqrt(1/2)
   switch (q) {
     case 0: return x;
-    case 1: return make_cx(fma(x.x, c1, x.y * s1), fma(x.y, c1, -x.x * s1));
-    case 2: return make_cx((x.x + x.y) * h, (x.y - x.x) * h);
-    case 3: return make_cx(fma(x.x, s1, x.y * c1), fma(x.y, s1, -x.x * c1));
-    case 4: return make_cx(x.y, -x.x);
-    case 5: return make_cx(fma(x.y, c1, -x.x * s1), -fma(x.x, c1, x.y * s1));
-    case 6: return make_cx((x.y - x.x) * h, -(x.x + x.y) * h);
-    default: return make_cx(fma(x.y, s1, -x.x * c1), -fma(x.x, s1, x.y * c1));
+    case 1: return make_float2(fmaf(x.x, c1, x.y * s1), fmaf(x.y, c1, -x.x * s1));
+    case 2: return make_float2((x.x + x.y) * h, (x.y - x.x) * h);
+    case 3: return make_float2(fmaf(x.x, s1, x.y * c1), fmaf(x.y, s1, -x.x * c1));
+    case 4: return make_float2(x.y, -x.x);
+    case 5: return make_float2(fmaf(x.y, c1, -x.x * s1), -fmaf(x.x, c1, x.y * s1));
+    case 6: return make_float2((x.y - x.x) * h, -(x.x + x.y) * h);
+    default: return make_float2(fmaf(x.y, s1, -x.x * c1), -fmaf(x.x, s1, x.y * c1));
   }
 }
 
 // In-register DFT of v[0, N), N in {2, 4, 8, 16}, natural order in and out:
 // radix-2 decimation in time on the bit-reversed copy.
 template <int N>
-__device__ __forceinline__ void dft_reg(cx* v) {
+__device__ __forceinline__ void dft_reg(cf* v) {
   constexpr int LOGN = N == 2 ? 1 : N == 4 ? 2 : N == 8 ? 3 : 4;
-  cx a[N];
+  cf a[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     int r = 0;
@@ -210,10 +220,10 @@ __device__ __forceinline__ void dft_reg(cx* v) {
     for (int i = 0; i < N; i += 2 * h) {
 #pragma unroll
       for (int p = 0; p < h; ++p) {
-        const cx t = rot16(a[i + p + h], p * (16 / (2 * h)));
-        const cx u = a[i + p];
-        a[i + p] = make_cx(u.x + t.x, u.y + t.y);
-        a[i + p + h] = make_cx(u.x - t.x, u.y - t.y);
+        const cf t = rot16(a[i + p + h], p * (16 / (2 * h)));
+        const cf u = a[i + p];
+        a[i + p] = make_float2(u.x + t.x, u.y + t.y);
+        a[i + p + h] = make_float2(u.x - t.x, u.y - t.y);
       }
     }
   }
@@ -222,16 +232,16 @@ __device__ __forceinline__ void dft_reg(cx* v) {
 }
 
 // W^m, W = exp(-2 pi i / L), m < L: the product of two table entries.
-__device__ __forceinline__ cx twiddle(const cx* thi, const cx* tlo, int32_t m) {
+__device__ __forceinline__ cf twiddle(const cf* thi, const cf* tlo, int32_t m) {
   return cmul(thi[m >> 6], tlo[m & (kTwLo - 1)]);
 }
 
 // v[r] *= W^(r k) for r in [1, 16): the base twiddles W^(k 2^b), b < 4,
 // from the table, the rest as products at most three deep.
-__device__ __forceinline__ void apply_twiddles(cx* v, const cx* thi, const cx* tlo, int32_t k) {
-  const cx w1 = twiddle(thi, tlo, k), w2 = twiddle(thi, tlo, 2 * k);
-  const cx w4 = twiddle(thi, tlo, 4 * k), w8 = twiddle(thi, tlo, 8 * k);
-  const cx w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
+__device__ __forceinline__ void apply_twiddles(cf* v, const cf* thi, const cf* tlo, int32_t k) {
+  const cf w1 = twiddle(thi, tlo, k), w2 = twiddle(thi, tlo, 2 * k);
+  const cf w4 = twiddle(thi, tlo, 4 * k), w8 = twiddle(thi, tlo, 8 * k);
+  const cf w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
   v[1] = cmul(v[1], w1);
   v[2] = cmul(v[2], w2);
   v[3] = cmul(v[3], w3);
@@ -264,11 +274,22 @@ __device__ __forceinline__ int32_t scatter_index(int32_t j, int r) {
   return (j / P::NS) * (P::NS * P::R) + (j % P::NS) + r * P::NS;
 }
 
+// The last pass leaves point t + j TPF in register j; the first pass takes
+// point t + m TPF + r L / R0 in register m R0 + r. Both are the points
+// t + i TPF, i < 16, so one transform's output feeds the next without
+// crossing LDS: first-pass register m R0 + r is last-pass register
+// m + r (16 / R0).
+template <int LOGL>
+__device__ __forceinline__ constexpr int last_of_first(int i) {
+  using P = PassCfg<LOGL, 0>;
+  return i / P::R + (i % P::R) * P::B;
+}
+
 // Twiddle and DFT of pass IP; v holds the gathered points. Passes with
 // NS > 1 are radix 16 with one butterfly per thread (j = t), twiddle
 // exponent k = (t mod NS) L / (16 NS).
 template <int LOGL, int IP>
-__device__ __forceinline__ void pass_compute(cx* v, int32_t t, const cx* thi, const cx* tlo) {
+__device__ __forceinline__ void pass_compute(cf* v, int32_t t, const cf* thi, const cf* tlo) {
   using P = PassCfg<LOGL, IP>;
   if constexpr (P::NS > 1)
     apply_twiddles(v, thi, tlo, (t % P::NS) * (FftCfg<LOGL>::L / (16 * P::NS)));
@@ -277,7 +298,7 @@ __device__ __forceinline__ void pass_compute(cx* v, int32_t t, const cx* thi, co
 }
 
 template <int LOGL, int IP>
-__device__ __forceinline__ void pass_scatter_lds(cx* buf, int32_t t, const cx* v) {
+__device__ __forceinline__ void pass_scatter_lds(cf* buf, int32_t t, const cf* v) {
   using P = PassCfg<LOGL, IP>;
 #pragma unroll
   for (int m = 0; m < P::B; ++m)
@@ -287,7 +308,7 @@ __device__ __forceinline__ void pass_scatter_lds(cx* buf, int32_t t, const cx* v
 }
 
 template <int LOGL, int IP>
-__device__ __forceinline__ void pass_gather_lds(const cx* buf, int32_t t, cx* v) {
+__device__ __forceinline__ void pass_gather_lds(const cf* buf, int32_t t, cf* v) {
   using P = PassCfg<LOGL, IP>;
 #pragma unroll
   for (int m = 0; m < P::B; ++m)
@@ -297,12 +318,13 @@ __device__ __forceinline__ void pass_gather_lds(const cx* buf, int32_t t, cx* v)
 
 // Passes IP..NP-1 of a transform whose points sit in v (already gathered
 // for pass IP). The last pass leaves its results in v, in the order of
-// scatter_index; every earlier pass crosses LDS.
+// scatter_index; every earlier pass crosses LDS, behind a barrier that also
+// orders it after the buffer's previous reads.
 template <int LOGL, int IP>
-__device__ __forceinline__ void fft_rest(cx* buf, int32_t t, cx* v, const cx* thi, const cx* tlo) {
+__device__ __forceinline__ void fft_rest(cf* buf, int32_t t, cf* v, const cf* thi, const cf* tlo) {
   pass_compute<LOGL, IP>(v, t, thi, tlo);
   if constexpr (IP + 1 < FftCfg<LOGL>::NP) {
-    __syncthreads();  // the buffer's previous contents are read
+    __syncthreads();
     pass_scatter_lds<LOGL, IP>(buf, t, v);
     __syncthreads();
     pass_gather_lds<LOGL, IP + 1>(buf, t, v);
@@ -336,6 +358,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* p, uint32
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes),
                                            kBufferWord3);
 }
+__device__ __forceinline__ float buf_load_f32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 __device__ __forceinline__ void buf_store_q(float x, __amdgpu_buffer_rsrc_t r, uint32_t off, float*) {
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, off, 0, 0);
 }
@@ -350,22 +375,31 @@ __device__ __forceinline__ void buf_store_q(float x, __amdgpu_buffer_rsrc_t r, u
   __builtin_amdgcn_raw_buffer_store_b16(h.bits, r, off, 0, 0);
 }
 
-// Rows travel in pairs, a as the real and b as the imaginary part of one
-// complex sequence; the spectrum of the kernel is real, so
-// IFFT(FFT(a + i b) H) = a * h + i b * h. The inverse is the forward
-// transform of the conjugate, conjugated, with 1/L folded into H.
+// First difference of the weighted row at pixel n < N (FP64, rounded once):
+// x(n) - x(n - 1), x(a) = e(a) w(a) (the adjoint leaves the row unweighted).
+// The load at n - 1 for n = 0 wraps to an out-of-range offset and reads 0.
+template <bool ADJ>
+__device__ __forceinline__ float row_diff(__amdgpu_buffer_rsrc_t r, RowWeight rw, double cu,
+                                          double du, int32_t n) {
+  const uint32_t off = static_cast<uint32_t>(n) * 4u;
+  const double e0 = buf_load_f32(r, off), e1 = buf_load_f32(r, off - 4u);
+  if (ADJ) return static_cast<float>(e0 - e1);
+  return static_cast<float>(e0 * pixel_weight(rw, cu, du, n) -
+                            e1 * pixel_weight(rw, cu, du, n - 1));
+}
+
 template <int LOGL, typename OutT, bool ADJ>
 __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
     GeoConst gc, RowBand rband, double du, double dv, double sdd, double tau, int kind,
     int64_t nrows, const float* __restrict__ e, OutT* __restrict__ q) {
   using C = FftCfg<LOGL>;
-  constexpr int P0R = PassCfg<LOGL, 0>::R;
-  extern __shared__ cx fbuf[];
+  constexpr int R0 = PassCfg<LOGL, 0>::R, B0 = PassCfg<LOGL, 0>::B;
+  extern __shared__ cf fbuf[];
   const int32_t g = static_cast<int32_t>(threadIdx.x) / C::TPF;
   const int32_t t = static_cast<int32_t>(threadIdx.x) % C::TPF;
-  cx* buf = fbuf + g * C::BUF;
-  cx* thi = fbuf + C::G * C::BUF;  // twiddle tables after the FFT buffers
-  cx* tlo = thi + C::THI;
+  cf* buf = fbuf + g * C::BUF;
+  cf* thi = fbuf + C::G * C::BUF;  // twiddle tables after the FFT buffers
+  cf* tlo = thi + C::THI;
   const int32_t nu = gc.nu;
   const double cu = gc.cu;
 
@@ -373,35 +407,71 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
     const int32_t m = i < C::THI ? 64 * i : i - C::THI;
     double sv, cv;
     sincospi(-2.0 * static_cast<double>(m) / C::L, &sv, &cv);
-    thi[i] = make_cx(cv, sv);  // tlo follows thi contiguously
+    thi[i] = make_float2(static_cast<float>(cv), static_cast<float>(sv));  // tlo follows thi
   }
-  __syncthreads();
 
-  // Kernel spectrum: FFT of the taps tau h(m), |m| < Nu, placed circularly;
-  // each thread keeps H (rounded to FP32) at the points it gathers in the
-  // inverse's first pass.
-  cx v[16];
+  // g(m) for m in [-N, N), FP64, at dg[m + N]: an inclusive scan of the
+  // taps over the workgroup (consecutive chunks per thread, then the chunk
+  // totals), in the FFT buffers: their G (L + L/16) points of 8 bytes hold
+  // the 2N + WG doubles (L >= 2N and G L / 16 = WG).
+  double* dg = reinterpret_cast<double*>(fbuf);
+  double* part = dg + 2 * nu;
+  {
+    const int32_t n2 = 2 * nu;
+    const int32_t chunk = (n2 + C::WG - 1) / C::WG;
+    const int32_t k0 = static_cast<int32_t>(threadIdx.x) * chunk;
+    double s = 0.0;
+    for (int32_t j = 0; j < chunk; ++j) {
+      const int32_t k = k0 + j;
+      if (k < n2) {
+        if (k > 0) s += tau * ramp_tap(kind, k - nu, tau);
+        dg[k] = s;
+      }
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int32_t off = 1; off < C::WG; off *= 2) {
+      const double p = threadIdx.x >= static_cast<uint32_t>(off) ? part[threadIdx.x - off] : 0.0;
+      __syncthreads();
+      part[threadIdx.x] += p;
+      __syncthreads();
+    }
+    const double before = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0.0;
+    for (int32_t j = 0; j < chunk; ++j) {
+      const int32_t k = k0 + j;
+      if (k < n2) dg[k] += before;
+    }
+    __syncthreads();
+  }
+
+  // G: FFT of g placed circularly (index m mod L). Each thread keeps
+  // conj(G) / L at the points it gathers in a transform's first pass, and
+  // g(n - N) at its output pixels n = t + j TPF, j < 8.
+  cf v[16];
 #pragma unroll
-  for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
+  for (int m = 0; m < B0; ++m)
 #pragma unroll
-    for (int r = 0; r < P0R; ++r) {
+    for (int r = 0; r < R0; ++r) {
       const int32_t n = gather_index<LOGL, 0>(t, m, r);
       const int32_t s = n < C::L / 2 ? n : n - C::L;
-      const double hv = (s > -nu && s < nu) ? tau * ramp_tap(kind, s, tau) : 0.0;
-      v[m * P0R + r] = make_cx(hv, 0.0);
+      const float gv = (s >= -nu && s < nu) ? static_cast<float>(dg[s + nu]) : 0.0f;
+      v[m * R0 + r] = make_float2(gv, 0.0f);
     }
-  fft_rest<LOGL, 0>(buf, t, v, thi, tlo);
-  __syncthreads();
-  pass_scatter_lds<LOGL, C::NP - 1>(buf, t, v);
-  __syncthreads();
-  float H[16];
+  float gend[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int32_t n = t + j * C::TPF;
+    gend[j] = n < nu ? static_cast<float>(dg[n]) : 0.0f;
+  }
+  fft_rest<LOGL, 0>(buf, t, v, thi, tlo);  // its first barrier follows every read of dg
+  cf gc_[16];
   {
-    constexpr double inv_l = 1.0 / static_cast<double>(C::L);
+    constexpr float inv_l = 1.0f / static_cast<float>(C::L);  // a power of two: exact
 #pragma unroll
-    for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
-#pragma unroll
-      for (int r = 0; r < P0R; ++r)
-        H[m * P0R + r] = static_cast<float>(buf[fpad(gather_index<LOGL, 0>(t, m, r))].x * inv_l);
+    for (int i = 0; i < 16; ++i) {
+      const cf x = v[last_of_first<LOGL>(i)];
+      gc_[i] = make_float2(x.x * inv_l, -x.y * inv_l);
+    }
   }
 
   // Row pairs are wave-uniform (an FFT spans whole waves), so each row is
@@ -424,57 +494,57 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
     const __amdgpu_buffer_rsrc_t ia = row_rsrc(e + (has_a ? rowa_in : 0), has_a ? nu * 4u : 0u);
     const __amdgpu_buffer_rsrc_t ib = row_rsrc(e + (has_b ? rowb_in : 0), has_b ? nu * 4u : 0u);
     const RowWeight wa = row_weight(gc, dv, sdd, ba), wb = row_weight(gc, dv, sdd, bb);
+    // c = x(N - 1), the last weighted pixel of each row.
+    const uint32_t last = static_cast<uint32_t>(nu - 1) * 4u;
+    double ca = buf_load_f32(ia, last), cb = buf_load_f32(ib, last);
+    if (!ADJ) {
+      ca *= pixel_weight(wa, cu, du, nu - 1);
+      cb *= pixel_weight(wb, cu, du, nu - 1);
+    }
 
-    // Forward transform; its first pass reads (and weights) the two rows.
-    // Points in the upper half (index >= L/2 >= Nu) are padding.
+    // Forward transform of y; points at or beyond N (the upper half and
+    // more) are zero.
 #pragma unroll
-    for (int m = 0; m < PassCfg<LOGL, 0>::B; ++m)
+    for (int m = 0; m < B0; ++m)
 #pragma unroll
-      for (int r = 0; r < P0R; ++r) {
-        double re = 0.0, im = 0.0;
-        if (r < P0R / 2) {
-          const int32_t n = gather_index<LOGL, 0>(t, m, r);
-          const uint32_t off = static_cast<uint32_t>(n) * 4u;
-          re = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ia, off, 0, 0));
-          im = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ib, off, 0, 0));
-          if (!ADJ) {
-            re *= pixel_weight(wa, cu, du, n);
-            im *= pixel_weight(wb, cu, du, n);
-          }
+      for (int r = 0; r < R0; ++r) {
+        float re = 0.0f, im = 0.0f;
+        const int32_t n = gather_index<LOGL, 0>(t, m, r);
+        if (r < R0 / 2 && n < nu) {
+          re = row_diff<ADJ>(ia, wa, cu, du, n);
+          im = row_diff<ADJ>(ib, wb, cu, du, n);
         }
-        v[m * P0R + r] = make_cx(re, im);
+        v[m * R0 + r] = make_float2(re, im);
       }
-    __syncthreads();  // the previous pair's last gather is done
     fft_rest<LOGL, 0>(buf, t, v, thi, tlo);
-    __syncthreads();
-    pass_scatter_lds<LOGL, C::NP - 1>(buf, t, v);
-    __syncthreads();
-    // Inverse: conj(X) H gathered for the first pass.
-    pass_gather_lds<LOGL, 0>(buf, t, v);
+    // Inverse: the forward transform of conj(Y G) / L, taken in registers
+    // (the last pass's points are the first pass's).
+    cf z[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const double hi = H[i];
-      v[i] = make_cx(v[i].x * hi, -v[i].y * hi);
+      const cf y = v[last_of_first<LOGL>(i)];
+      z[i] = cmul(make_float2(y.x, -y.y), gc_[i]);
     }
-    fft_rest<LOGL, 0>(buf, t, v, thi, tlo);
+    fft_rest<LOGL, 0>(buf, t, z, thi, tlo);
     // The last pass has one radix-16 butterfly per thread (j = t, NS = L/16):
-    // result r is point t + r L/16, so the stores are coalesced; only the
-    // lower half (r < 8) holds row pixels.
+    // result j is point t + j L/16, so the stores are coalesced; only the
+    // lower half (j < 8) holds row pixels.
     const __amdgpu_buffer_rsrc_t oa =
         row_rsrc(q + (has_a ? rowa_out : 0), has_a ? nu * static_cast<uint32_t>(sizeof(OutT)) : 0u);
     const __amdgpu_buffer_rsrc_t ob =
         row_rsrc(q + (has_b ? rowb_out : 0), has_b ? nu * static_cast<uint32_t>(sizeof(OutT)) : 0u);
+    const float fca = static_cast<float>(ca), fcb = static_cast<float>(cb);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int32_t n = scatter_index<LOGL, C::NP - 1>(t, r);
-      double ya = v[r].x, yb = -v[r].y;
+    for (int j = 0; j < 8; ++j) {
+      const int32_t n = t + j * C::TPF;
+      float ya = fmaf(-fca, gend[j], z[j].x), yb = fmaf(-fcb, gend[j], -z[j].y);
       if (ADJ) {
-        ya *= pixel_weight(wa, cu, du, n);
-        yb *= pixel_weight(wb, cu, du, n);
+        ya = static_cast<float>(ya * pixel_weight(wa, cu, du, n));
+        yb = static_cast<float>(yb * pixel_weight(wb, cu, du, n));
       }
       const uint32_t off = static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(OutT));
-      buf_store_q(static_cast<float>(ya), oa, off, static_cast<OutT*>(nullptr));
-      buf_store_q(static_cast<float>(yb), ob, off, static_cast<OutT*>(nullptr));
+      buf_store_q(ya, oa, off, static_cast<OutT*>(nullptr));
+      buf_store_q(yb, ob, off, static_cast<OutT*>(nullptr));
     }
   }
 }
@@ -483,7 +553,7 @@ template <int LOGL, typename OutT, bool ADJ>
 int launch_fft(const GeoConst& gc, const RowBand& rb, double du, double dv, double sdd, double tau,
                int kind, int64_t nrows, const float* e, OutT* q, hipStream_t st) {
   using C = FftCfg<LOGL>;
-  const size_t lds = (static_cast<size_t>(C::G) * C::BUF + C::THI + kTwLo) * sizeof(cx);
+  const size_t lds = (static_cast<size_t>(C::G) * C::BUF + C::THI + kTwLo) * sizeof(cf);
   auto kern = &filter_fft_kernel<LOGL, OutT, ADJ>;
   if (lds > 65536) {
     const hipError_t err = raise_lds_limit<&filter_fft_kernel<LOGL, OutT, ADJ>>(lds);
