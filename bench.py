@@ -54,17 +54,18 @@ N_CU, CLOCK_HZ, VALU_LANES_PER_CLK = 256, 2.4e9, 64
 # 151.7 B/clk/CU at 2.4 GHz (above the 128 B/clk of the previous generation).
 LDS_BYTES_PER_CLK = 151.7
 HBM_PEAK = 8.0e12
-# VALU work per voxel-view update of the mirrored, cell-staged scheme: per
-# voxel pair v, truncation, fraction and cell address (4, shared); per voxel
-# the cell's bilinear form q + du q_u + fr (q_v + du q_uv) (3 FMAs) and the
-# weighted accumulate (1): (4 + 2 * 4) / 2 = 6.
-VALU_OPS_PER_UPDATE = 6.0
-LDS_BYTES_PER_UPDATE = 16.0  # one 16-byte cell (q, q_u, q_v, q_uv) per voxel
-# The adjoint's scheme: per voxel W x (1), the row split (2) and the four tap
-# weights (4); per voxel pair v, truncation and fraction (3, shared); the
-# adds themselves are LDS atomics: 7 + 1.5 = 8.5 VALU ops and four 4-byte
-# LDS read-modify-writes per update.
-ADJ_VALU_OPS_PER_UPDATE = 8.5
+# VALU work per voxel-view update of the mirrored, difference-staged scheme:
+# per voxel pair v, truncation, fraction and tap address (4, shared); per
+# voxel two u-interpolations (1 FMA each on the staged difference), one
+# v-interpolation (2) and the weighted accumulate (1): (4 + 2 * 5) / 2 = 7.
+VALU_OPS_PER_UPDATE = 7.0
+LDS_BYTES_PER_UPDATE = 16.0  # 4 FP32 taps (value and u-difference of two rows)
+# The adjoint's scheme (32-bit fixed-point tile): per voxel W S x (1), the row
+# split (2), the four tap weights (4) and their conversions (4); per voxel
+# pair v, truncation and fraction (3, shared); the adds themselves are LDS
+# atomics: 11 + 1.5 = 12.5 VALU ops and four 4-byte LDS read-modify-writes
+# per update.
+ADJ_VALU_OPS_PER_UPDATE = 12.5
 ADJ_LDS_BYTES_PER_UPDATE = 32.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "bp_tiled_mirror_kernel_bp2048_traffic.json")
 # Slab workload: views are filtered in 16-view chunks; two contiguous chunks

@@ -105,165 +105,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   // unrolling, so this selects a register.
   auto slice_acc = [&](int t) -> float& { return t < kBrickZ ? acc[t] : accm[t - kBrickZ]; };
 
-  if constexpr (TILED && MIRROR) {
-    // Cells: entry (c, r) of view sl is two float4 at byte
-    // (sl slot + c tvp + r) kCellBytes: (q, q_u, q_v, q_uv) of the cell between
-    // rows org_v + r and org_v + r + 1 at column org_u + c, then the same
-    // terms between the mirror rows G - org_v - r and G - org_v - r - 1. A
-    // voxel at row n + fr (tile-relative) samples its cell as
-    // q + du q_u + fr (q_v + du q_uv), its mirror voxel the mirror cell with
-    // the same du and fr (Theorem 1).
-    const int32_t tu = ts.tu, tvp = ts.tvp, rstep = ts.rstep, rows = ts.rows;
-    const int32_t tv = ts.tv, ncell = ts.tv - 1;
-    const int32_t slot_entries = tu * tvp;
-    // Staging assignment: thread -> tile column sc and the consecutive cells
-    // r0 .. r0 + rows - 1, from rows r0 .. r0 + rows (lanes along u, so
-    // global reads are coalesced).
-    const int32_t sr = tid / tu, sc = tid - sr * tu;
-    const bool stager = sr < rstep;
-    const int32_t r0 = sr * rows;
-    const uint32_t es = sizeof(T);
-    const uint32_t row_es = static_cast<uint32_t>(gc.nu) * es;
-    const uint32_t nrec = static_cast<uint32_t>(gc.nu) * static_cast<uint32_t>(gc.nv) * es;
-    constexpr int NSLOT = kPrefetchSlots;
-    // Raw bits of (q(u), q(u+1)) of a row and of its mirror row.
-    uint4 pre[NSLOT];
-
-    // Issue the loads of views [s0, s0 + nvc): rows + 1 rows per view.
-    // Views whose tile lies on the detector skip the range checks.
-    auto load_stage = [&](int32_t s0, int32_t nvc) {
-      int32_t sl = 0, rr = 0;
-      int32_t org_v = 0, inside = 0;
-      uint32_t c0 = 0, c1 = 0, off = 0, offm = 0;
-#pragma unroll
-      for (int m = 0; m < NSLOT; ++m) {
-        if (sl < nvc) {
-          // The descriptor is rebuilt per slot (scalar work): carried across
-          // slots, the compiler moves it to vector registers and wraps each
-          // load in a loop over lanes.
-          const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-              const_cast<T*>(q + (s0 + sl) * vstride), 0, nrec, kBufferWord3);
-          if (rr == 0) {  // uniform: new view
-            const int32_t s = s0 + sl;
-            const int32_t gu = bvs[s].org_u + sc;
-            org_v = bvs[s].org_v;
-            inside = __builtin_amdgcn_readfirstlane(bvs[s].inside);
-            c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
-                     ? static_cast<uint32_t>(gu) * es : kBadCol;
-            c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
-                     ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
-            off = static_cast<uint32_t>(org_v + r0) * row_es + c0;
-            offm = static_cast<uint32_t>(gc.mirror_g - org_v - r0) * row_es + c0;
-          }
-          // As in the plain variant, the loads are issued unconditionally;
-          // a lane with no row here reads at an out-of-range offset, which
-          // returns zero without a fetch.
-          const int32_t r = r0 + rr;
-          const bool on = stager && r < tv;
-          uint32_t o0, o1, m0, m1;
-          if (inside) {
-            o0 = on ? off : kBadRow;
-            o1 = o0 + es;
-            m0 = on ? offm : kBadRow;
-            m1 = m0 + es;
-          } else {
-            const int32_t gr = org_v + r, gm = gc.mirror_g - gr;
-            const uint32_t ro = on && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
-                                    ? static_cast<uint32_t>(gr) * row_es : kBadRow;
-            const uint32_t rm = on && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
-                                    ? static_cast<uint32_t>(gm) * row_es : kBadRow;
-            o0 = ro + c0;
-            o1 = ro + c1;
-            m0 = rm + c0;
-            m1 = rm + c1;
-          }
-          uint4 p;
-          p.x = buf_load_raw<T>(rsrc, o0);
-          p.y = buf_load_raw<T>(rsrc, o1);
-          p.z = buf_load_raw<T>(rsrc, m0);
-          p.w = buf_load_raw<T>(rsrc, m1);
-          pre[m] = p;
-          off += row_es;
-          offm -= row_es;
-        }
-        if (++rr == rows + 1) {
-          rr = 0;
-          ++sl;
-        }
-      }
-    };
-
-    // Cell r0 + rr of a view from its rows rr (slot m) and rr + 1 (slot m + 1).
-    auto store_stage = [&](int32_t nvc) {
-      int32_t sl = 0, rr = 0;
-#pragma unroll
-      for (int m = 0; m + 1 < NSLOT; ++m) {
-        if (sl < nvc && rr < rows) {
-          const int32_t r = r0 + rr;
-          if (stager && r < ncell) {
-            const float a0 = raw_to_f32<T>(pre[m].x), a1 = raw_to_f32<T>(pre[m].y);
-            const float b0 = raw_to_f32<T>(pre[m + 1].x), b1 = raw_to_f32<T>(pre[m + 1].y);
-            const float c0 = raw_to_f32<T>(pre[m].z), c1 = raw_to_f32<T>(pre[m].w);
-            const float d0 = raw_to_f32<T>(pre[m + 1].z), d1 = raw_to_f32<T>(pre[m + 1].w);
-            const float qu = a1 - a0, mu = c1 - c0;
-            float4* cell = tile + 2 * (sl * slot_entries + sc * tvp + r);
-            cell[0] = make_float4(a0, qu, b0 - a0, (b1 - b0) - qu);
-            cell[1] = make_float4(c0, mu, d0 - c0, (d1 - d0) - mu);
-          }
-        }
-        if (++rr == rows + 1) {
-          rr = 0;
-          ++sl;
-        }
-      }
-    };
-
-    const char* tile_bytes = reinterpret_cast<const char*>(tile);
-    load_stage(0, min(ts.vc, vb.nviews));
-    for (int32_t s0 = 0; s0 < vb.nviews; s0 += ts.vc) {
-      const int32_t nvc = min(ts.vc, vb.nviews - s0);
-      if (s0 > 0) __syncthreads();  // the previous views' tiles are consumed
-      store_stage(nvc);
-      __syncthreads();
-      if (s0 + ts.vc < vb.nviews) load_stage(s0 + ts.vc, min(ts.vc, vb.nviews - s0 - ts.vc));
-      for (int32_t sl = 0; sl < nvc; ++sl) {
-        const ColumnF32 c = column_f32(bvs[s0 + sl], txf, tyf, kvf);
-        const uint32_t nu = min(c.nu, static_cast<uint32_t>(tu - 1));
-        // One register holds the column's tile offset, so each pair's
-        // address is a single shift-and-add.
-        uint32_t cbase = (static_cast<uint32_t>(sl * slot_entries) +
-                          nu * static_cast<uint32_t>(tvp) + c.nvb) * kCellBytes;
-        asm volatile("" : "+v"(cbase));
-        const char* pb = tile_bytes + cbase;
-        // Reads run one voxel pair ahead of use, so LDS latency overlaps the
-        // previous pair's arithmetic.
-        uint32_t dn;
-        float fr;
-        voxel_row_off(c.fvb, c.dvk, 0, &dn, &fr);
-        float4 M = reinterpret_cast<const float4*>(pb + dn * kCellBytes)[0];
-        float4 Mm = reinterpret_cast<const float4*>(pb + dn * kCellBytes)[1];
-#pragma unroll
-        for (int t = 0; t < kBrickZ; ++t) {
-          float4 Mn = M, Mmn = Mm;
-          uint32_t dn1 = 0;
-          float fr1 = 0.0f;
-          if (t + 1 < kBrickZ) {
-            voxel_row_off(c.fvb, c.dvk, t + 1, &dn1, &fr1);
-            const float4* p = reinterpret_cast<const float4*>(pb + dn1 * kCellBytes);
-            Mn = p[0];
-            Mmn = p[1];
-          }
-          const float sv = fmaf(fr, fmaf(c.du, M.w, M.z), fmaf(c.du, M.y, M.x));
-          acc[t] = fmaf(c.w, sv, acc[t]);
-          const float sm = fmaf(fr, fmaf(c.du, Mm.w, Mm.z), fmaf(c.du, Mm.y, Mm.x));
-          accm[t] = fmaf(c.w, sm, accm[t]);
-          M = Mn;
-          Mm = Mmn;
-          fr = fr1;
-        }
-      }
-    }
-  } else if constexpr (TILED) {
+  if constexpr (TILED) {
     const int32_t tu = ts.tu, tv = ts.tv, tvp = ts.tvp, rstep = ts.rstep, rows = ts.rows;
     const int32_t slot_entries = tu * tvp;
     // Staging assignment: thread -> tile column sc and rows sr + m * rstep
@@ -543,7 +385,7 @@ int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, co
   const dim3 grid(static_cast<uint32_t>(nwg)), block(kThreads);
   if (ts.vc > 0) {
     const size_t lds = static_cast<size_t>(ts.vc) * ts.tu * ts.tvp *
-                       (run.mirror ? kCellBytes : kPlainEntryBytes);
+                       (run.mirror ? kTileEntryBytes : kPlainEntryBytes);
     if (run.mirror)
       hipLaunchKernelGGL((bp_tiled_mirror_kernel<T>), grid, block, lds, st, gc, run, vb, ts,
                          qt, vstride, vol, scale, accumulate);

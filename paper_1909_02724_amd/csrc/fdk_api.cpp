@@ -326,8 +326,8 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
     const char* qb = static_cast<const char*>(q) + (size_t)b * vstride * dtype_size(q_dtype);
     for (const fdk::SliceRun& r : sl.runs) {
       const fdk::TileShape ts =
-          r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kCellBytes,
-                                     fdk::kPrefetchSlots, direct, true)
+          r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
+                                     fdk::kPrefetchSlots, direct)
                    : fdk::tile_shape(g, gc, r, vb, fdk::kPlainBrickZ, fdk::kPlainEntryBytes,
                                      fdk::kPlainPrefetchSlots, direct);
       if (int e = fdk::launch_backproject(gc, r, vb, ts, qb, q_dtype, vstride, vol, scale,

@@ -61,18 +61,12 @@ constexpr int kBrickThreads = kBrickX * kBrickY;
 constexpr int kMaxStageViews = 3;
 constexpr int kPrefetchSlots = 9;       // tile entries a thread prefetches per stage
 constexpr int kTileLdsBytes = 36864;    // LDS budget for the tiles of one stage
-constexpr int kTileEntryBytes = 16;     // (q, dq/du) of a row and of its mirror row (adjoint sizing)
-// Mirrored back-projection tiles hold cells instead of rows: the bilinear
-// terms (q, q_u, q_v, q_uv) of the cell between a row and the next one, and
-// of the cell between its mirror row and the mirror of the next one.
-constexpr int kCellBytes = 32;
+constexpr int kTileEntryBytes = 16;     // (q, dq/du) of a row and of its mirror row
 
 struct TileShape {
   int32_t tu, tv, tvp;   // tile columns, rows, and the (odd) column pitch in entries
   int32_t vc;            // views staged at once; 0 selects the direct variant
-  // Staging: rows (cells) advanced per pass and passes per view; with
-  // cells, a thread stages `rows` consecutive cells from rows + 1 rows.
-  int32_t rstep, rows;
+  int32_t rstep, rows;   // staging: rows advanced per pass, passes per view
   int32_t nbx, nby, nseg;  // bricks along x, y and z-segments of the run
   // Adjoint: lane (tx, ty) visits its slots from (rot_a tx + rot_b (ty mod 4))
   // mod 16 on, which spreads the lanes' LDS adds over the banks.
@@ -83,11 +77,10 @@ struct TileShape {
 // exceeds the LDS or prefetch budget, or the caller asks for the direct
 // variant (FDK_DIRECT).
 // bz: slices per brick; entry_bytes: LDS bytes per tile entry; slots: tile
-// rows a thread prefetches per stage; cells: the tile holds the tv - 1 cells
-// between consecutive rows (pitch (tv - 1) | 1) instead of the tv rows.
+// entries a thread prefetches per stage.
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots,
-                     bool direct, bool cells = false);
+                     bool direct);
 // Plain (unmirrored) back-projection runs: 32 slices per brick, the tile
 // holding (q, dq/du) of the main rows only; a prefetch slot holds one row's
 // pair instead of two, so twice as many fit the same registers.

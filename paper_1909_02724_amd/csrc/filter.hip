@@ -340,7 +340,8 @@ struct RowWeight {
 };
 __device__ __forceinline__ RowWeight row_weight(const GeoConst& gc, double dv, double sdd, int32_t b) {
   const double bb = (b - gc.cv) * dv;
-  return RowWeight{sdd, sdd * sdd + bb * bb};
+  const double d2 = sdd * sdd;
+  return RowWeight{sdd, fma(bb, bb, d2)};
 }
 __device__ __forceinline__ double pixel_weight(RowWeight rw, double cu, double du, int32_t a) {
   const double x = (static_cast<double>(a) - cu) * du;
@@ -384,8 +385,11 @@ __device__ __forceinline__ float row_diff(__amdgpu_buffer_rsrc_t r, RowWeight rw
   const uint32_t off = static_cast<uint32_t>(n) * 4u;
   const double e0 = buf_load_f32(r, off), e1 = buf_load_f32(r, off - 4u);
   if (ADJ) return static_cast<float>(e0 - e1);
-  return static_cast<float>(e0 * pixel_weight(rw, cu, du, n) -
-                            e1 * pixel_weight(rw, cu, du, n - 1));
+  // Separate statements: neither product fuses into the difference, so
+  // every instantiation rounds the same way.
+  const double x0 = e0 * pixel_weight(rw, cu, du, n);
+  const double x1 = e1 * pixel_weight(rw, cu, du, n - 1);
+  return static_cast<float>(x0 - x1);
 }
 
 template <int LOGL, typename OutT, bool ADJ>
@@ -542,6 +546,10 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
         ya = static_cast<float>(ya * pixel_weight(wa, cu, du, n));
         yb = static_cast<float>(yb * pixel_weight(wb, cu, du, n));
       }
+      // The FP32 result is rounded as such before any 16-bit store: without
+      // the barrier the FMA fuses into a mixed-precision one that rounds once
+      // to 16 bits, which can differ from the FP32 output rounded.
+      asm volatile("" : "+v"(ya), "+v"(yb));
       const uint32_t off = static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(OutT));
       buf_store_q(ya, oa, off, static_cast<OutT*>(nullptr));
       buf_store_q(yb, ob, off, static_cast<OutT*>(nullptr));

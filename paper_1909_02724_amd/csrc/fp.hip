@@ -17,9 +17,9 @@ namespace {
 
 // Tiled variant: per view, the brick's splats accumulate in LDS tiles with
 // the back-projector's transposed layout (one more column, for the u + 1
-// taps), one plane for main rows and one for mirror rows, as FP32 LDS
-// atomics; the tiles are then added to the projection with one global
-// atomic per non-zero pixel. Direct variant: global atomics per tap.
+// taps), one plane for main rows and one for mirror rows, as 32-bit fixed
+// point (FP32 for bricks that need it); the tiles are then added to the
+// projection with one global atomic per non-zero pixel. Direct variant: global atomics per tap.
 
 __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_t nv, int32_t a,
                                       float du, int32_t ra, int32_t rb, float fr, float val) {
@@ -70,14 +70,51 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
   }
 }
 
-// Accumulation for the tiled adjoint: the splats of a brick and view add
-// into LDS tiles in FP32 (ds_add_f32), so each pixel's sum carries FP32
-// rounding relative to its own contributions (whatever their spread in
-// magnitude across the brick), and NaN and infinities reach exactly the
-// pixels their voxels touch. The order of the adds within a tile, and of
-// the tiles' adds into the projection, is not fixed: results are
-// reproducible to rounding, not bitwise.
+// Accumulation for the tiled adjoint. LDS float atomics are serialised on
+// gfx950: about 3 clocks per active lane per CU, 194 per full wave, against
+// 5 for an integer add of any width or lane count (measured). A brick's
+// splats therefore accumulate as 32-bit fixed point with integer LDS
+// atomics (exact and independent of order within the workgroup), unless
+// the brick is one of the two kinds fixed point cannot serve:
+//  - it holds a NaN or an infinity, which integers cannot carry; or
+//  - it spans a wide dynamic range: more than 1 % of its non-zero voxels lie
+//    below 2^-13 of its largest magnitude.
+// Those bricks take FP32 atomics (float tile, same layout), so each pixel's
+// sum carries FP32 rounding relative to its own contributions and
+// non-finite values reach exactly the pixels they touch.
+//
+// Fixed-point scale, per brick and view, from a bound on what one pixel can
+// receive:
+//  - a column adds to the pixel columns floor(u) and floor(u) + 1, so pixel
+//    column p hears only from columns with floor(u) in {p - 1, p};
+//  - of a column's slices in the brick (16, or 32 for a plain run), those
+//    with a tap on row r have v in [r - 1, r + 1): at most
+//    floor(2 / (dv/dk)) + 2 of them (one spare for the rounding of v), and
+//    never more than the brick's slice count;
+//  - each contribution is at most M = max over columns of max|x| * W.
+// A histogram over floor(u) of the per-column slot bounds gives K, the most
+// contributions any pixel can receive; S = 2^(31 - e) with 1.01 K M < 2^e
+// keeps every partial sum, rounding included, inside int32. S is a power of
+// two, so the scaling is exact and cannot overflow however small or large
+// the values. A pixel's quantisation error is at most half a unit,
+// 2^(e - 32) ~ K M 2^-31, per contribution: relative to the brick's largest
+// splat, not to the pixel's own sum, which is why wide-range bricks go to
+// FP32.
+constexpr int32_t kHistStride = kThreads;  // tile columns tu + 1 <= 256
 constexpr int64_t kFpSplitTarget = 4096;    // workgroups below which views are split
+constexpr int kFpWideRangeLog2 = 13;        // "small" voxels: below 2^-13 of the brick's max
+constexpr int kFpWideRangePct = 1;          // FP32 path above 1 % small voxels
+
+// FP32 splat (FP32 path): taps (u, n), (u + 1, n), (u, n + 1),
+// (u + 1, n + 1) of a tile with column pitch tvp.
+__device__ __forceinline__ void splat_f32(float* p, int32_t tvp, float val, float fr, float du) {
+  const float fb = val * fr, fa = val - fb;
+  const float du0 = 1.0f - du;
+  atomicAdd(p, fa * du0);
+  atomicAdd(p + tvp, fa * du);
+  atomicAdd(p + 1, fb * du0);
+  atomicAdd(p + tvp + 1, fb * du);
+}
 
 template <bool MIRROR>
 __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRun run,
@@ -85,9 +122,11 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
                                                             const float* __restrict__ vol,
                                                             float* __restrict__ q,
                                                             int64_t vstride, float scale) {
-  extern __shared__ float atile[];
+  extern __shared__ int atile[];
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
-  __shared__ int any_nonzero;
+  __shared__ uint32_t hist[kMaxStageViews * kHistStride];
+  __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
+  __shared__ uint32_t amax_bits, n_nonzero, n_small, nonfinite;
   const int32_t tid = threadIdx.x;
   constexpr int BZ = MIRROR ? kBrickZ : kPlainBrickZ;  // slices per brick
   // blockIdx.y picks this workgroup's share of the launch's views: small
@@ -99,20 +138,41 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   const int32_t v_hi = min(vb.nviews, v_lo + per);
   if (v_lo >= v_hi) return;  // uniform, before any barrier
   const BrickCoords bc = brick_coords(gc, run, ts, BZ);
-  if (tid == 0) any_nonzero = 0;
+  if (tid == 0) amax_bits = n_nonzero = n_small = nonfinite = 0u;
   if (tid >= v_lo && tid < v_hi)
     bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
                            MIRROR);
   const uint32_t rot = slot_rotation(ts);
   float x[kBrickZ], xm[kBrickZ];
   load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
-  bool nz = false;  // NaN compares unequal to zero, so it counts
+  // Brick statistics: largest magnitude, non-finite values (x - x is NaN
+  // exactly for those), then how many non-zero voxels are small against it.
+  float amax = 0.0f;
+  bool bad = false;
 #pragma unroll
-  for (int t = 0; t < kBrickZ; ++t) nz = nz || (x[t] != 0.0f) || (xm[t] != 0.0f);
+  for (int t = 0; t < kBrickZ; ++t) {
+    amax = fmaxf(amax, fmaxf(fabsf(x[t]), fabsf(xm[t])));
+    bad = bad || ((x[t] - x[t]) != 0.0f) || ((xm[t] - xm[t]) != 0.0f);
+  }
   __syncthreads();
-  if (nz) any_nonzero = 1;
+  atomicMax(&amax_bits, __float_as_uint(amax));  // non-negative floats order as integers
+  if (bad) nonfinite = 1u;
   __syncthreads();
-  if (!any_nonzero) return;  // an all-zero brick adds nothing (uniform)
+  {
+    const float small = ldexpf(__uint_as_float(amax_bits), -kFpWideRangeLog2);
+    uint32_t nz = 0, ns = 0;
+#pragma unroll
+    for (int t = 0; t < kBrickZ; ++t) {
+      nz += (x[t] != 0.0f) + (xm[t] != 0.0f);
+      ns += (x[t] != 0.0f && fabsf(x[t]) < small) + (xm[t] != 0.0f && fabsf(xm[t]) < small);
+    }
+    if (nz) atomicAdd(&n_nonzero, nz);
+    if (ns) atomicAdd(&n_small, ns);
+  }
+  __syncthreads();
+  if (amax_bits == 0u && nonfinite == 0u) return;  // an all-zero brick adds nothing (uniform)
+  const bool fp32_path =
+      nonfinite != 0u || 100u * n_small > static_cast<uint32_t>(kFpWideRangePct) * n_nonzero;
 
   const float kvf = static_cast<float>(gc.kv);
   const int32_t tuf = ts.tu + 1, tv = ts.tv, tvp = ts.tvp;
@@ -122,54 +182,104 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   for (int32_t s0 = v_lo; s0 < v_hi; s0 += ts.vc) {
     const int32_t nvc = min(ts.vc, v_hi - s0);
     // Main rows in planes [0, vc) and mirror rows in planes [vc, 2 vc), one
-    // word per pixel: all LDS banks serve the adds.
-    float* const mtile = atile + ts.vc * slot;
+    // 32-bit word per pixel: all LDS banks serve the adds (interleaved
+    // (main, mirror) pairs reached only half of them and conflicted 10-way).
+    int* const mtile = atile + ts.vc * slot;
     for (int32_t e = tid; e < nvc * slot; e += kThreads) {
-      atile[e] = 0.0f;
-      if (MIRROR) mtile[e] = 0.0f;
+      atile[e] = 0;
+      if (MIRROR) mtile[e] = 0;
+    }
+    if (!fp32_path) {
+      for (int32_t e = tid; e < nvc * kHistStride; e += kThreads) hist[e] = 0u;
+      if (tid < nvc) kcount[tid] = mbits[tid] = 0u;
     }
     __syncthreads();
+    if (!fp32_path) {
+      // Bounds: histogram of the columns' slot bounds over floor(u), and
+      // the largest contribution.
+      if (bc.owner) {
+        for (int32_t sl = 0; sl < nvc; ++sl) {
+          const ColumnF32 c = column_f32(bvs[s0 + sl], bc.txf, bc.tyf, kvf);
+          const uint32_t nu = min(c.nu, static_cast<uint32_t>(ts.tu - 1));
+          const float ks = fminf(static_cast<float>(BZ), floorf(2.0f / c.dvk) + 2.0f);
+          atomicAdd(&hist[sl * kHistStride + nu], static_cast<uint32_t>(ks));
+          atomicMax(&mbits[sl], __float_as_uint(amax * c.w));
+        }
+      }
+      __syncthreads();
+      if (tid < tuf) {
+        for (int32_t sl = 0; sl < nvc; ++sl) {
+          const uint32_t* h = hist + sl * kHistStride;
+          atomicMax(&kcount[sl], (tid < ts.tu ? h[tid] : 0u) + (tid > 0 ? h[tid - 1] : 0u));
+        }
+      }
+      __syncthreads();
+    }
     if (bc.owner) {
       for (int32_t sl = 0; sl < nvc; ++sl) {
         const ColumnF32 c = column_f32(bvs[s0 + sl], bc.txf, bc.tyf, kvf);
         const uint32_t nu = min(c.nu, static_cast<uint32_t>(ts.tu - 1));
-        float* const base = atile + sl * slot + nu * tvp + c.nvb;
-        float* const base1 = base + tvp;  // pixel column u + 1
-        float* const mbase = mtile + sl * slot + nu * tvp + c.nvb;
-        float* const mbase1 = mbase + tvp;
-        const float du0 = 1.0f - c.du;
+        if (!fp32_path) {
+          const float km = 1.01f * static_cast<float>(kcount[sl]) * __uint_as_float(mbits[sl]);
+          if (!(km > 0.0f)) continue;  // nothing reaches this view (uniform)
+          int e;
+          frexpf(km, &e);
+          const float ws = ldexpf(c.w, 31 - e);  // W S, S = 2^(31 - e)
+          int* const base = atile + sl * slot + nu * tvp + c.nvb;
+          int* const base1 = base + tvp;  // pixel column u + 1
+          int* const mbase = mtile + sl * slot + nu * tvp + c.nvb;
+          int* const mbase1 = mbase + tvp;
+          const float du0 = 1.0f - c.du;
 #pragma unroll
-        for (int t = 0; t < kBrickZ; ++t) {
-          uint32_t dn;
-          float fr;
-          voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
-          // Bilinear split (Alg. 3 transposed): rows n and n + 1 take
-          // 1 - fr and fr, columns u and u + 1 take 1 - du and du.
-          const float val = c.w * x[t];
-          const float wb = val * fr, wa = val - wb;
-          atomicAdd(base + dn, wa * du0);
-          atomicAdd(base1 + dn, wa * c.du);
-          atomicAdd(base + dn + 1, wb * du0);
-          atomicAdd(base1 + dn + 1, wb * c.du);
-          if (MIRROR) {
-            const float vm = c.w * xm[t];
-            const float mb = vm * fr, ma = vm - mb;
-            atomicAdd(mbase + dn, ma * du0);
-            atomicAdd(mbase1 + dn, ma * c.du);
-            atomicAdd(mbase + dn + 1, mb * du0);
-            atomicAdd(mbase1 + dn + 1, mb * c.du);
-          } else {
-            // The brick's upper 16 slices, into the same plane.
-            uint32_t dn2;
-            float fr2;
-            voxel_row_off(c.fvb, c.dvk, kBrickZ + static_cast<int32_t>((t + rot) & (kBrickZ - 1)),
-                          &dn2, &fr2);
-            const float v2 = c.w * xm[t];
-            const float b2 = v2 * fr2, a2 = v2 - b2;
-            atomicAdd(base + dn2, a2 * du0);
-            atomicAdd(base1 + dn2, a2 * c.du);
-            atomicAdd(base + dn2 + 1, b2 * du0);
-            atomicAdd(base1 + dn2 + 1, b2 * c.du);
+          for (int t = 0; t < kBrickZ; ++t) {
+            uint32_t dn;
+            float fr;
+            voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
+            const float val = ws * x[t];
+            const float wa = val - val * fr, wb = val * fr;
+            atomicAdd(base + dn, __float2int_rn(wa * du0));
+            atomicAdd(base1 + dn, __float2int_rn(wa * c.du));
+            atomicAdd(base + dn + 1, __float2int_rn(wb * du0));
+            atomicAdd(base1 + dn + 1, __float2int_rn(wb * c.du));
+            if (MIRROR) {
+              const float vm = ws * xm[t];
+              const float ma = vm - vm * fr, mb = vm * fr;
+              atomicAdd(mbase + dn, __float2int_rn(ma * du0));
+              atomicAdd(mbase1 + dn, __float2int_rn(ma * c.du));
+              atomicAdd(mbase + dn + 1, __float2int_rn(mb * du0));
+              atomicAdd(mbase1 + dn + 1, __float2int_rn(mb * c.du));
+            } else {
+              // The brick's upper 16 slices, into the same plane.
+              uint32_t dn2;
+              float fr2;
+              voxel_row_off(c.fvb, c.dvk,
+                            kBrickZ + static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn2, &fr2);
+              const float v2 = ws * xm[t];
+              const float a2 = v2 - v2 * fr2, b2 = v2 * fr2;
+              atomicAdd(base + dn2, __float2int_rn(a2 * du0));
+              atomicAdd(base1 + dn2, __float2int_rn(a2 * c.du));
+              atomicAdd(base + dn2 + 1, __float2int_rn(b2 * du0));
+              atomicAdd(base1 + dn2 + 1, __float2int_rn(b2 * c.du));
+            }
+          }
+        } else {
+          float* const fbase = reinterpret_cast<float*>(atile) + sl * slot + nu * tvp + c.nvb;
+          float* const fmbase = reinterpret_cast<float*>(mtile) + sl * slot + nu * tvp + c.nvb;
+#pragma unroll
+          for (int t = 0; t < kBrickZ; ++t) {
+            uint32_t dn;
+            float fr;
+            voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
+            splat_f32(fbase + dn, tvp, c.w * x[t], fr, c.du);
+            if (MIRROR) {
+              splat_f32(fmbase + dn, tvp, c.w * xm[t], fr, c.du);
+            } else {
+              uint32_t dn2;
+              float fr2;
+              voxel_row_off(c.fvb, c.dvk,
+                            kBrickZ + static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn2, &fr2);
+              splat_f32(fbase + dn2, tvp, c.w * xm[t], fr2, c.du);
+            }
           }
         }
       }
@@ -182,15 +292,22 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
         const int32_t s = s0 + sl;
         const int32_t gu = bvs[s].org_u + sc;
         if (static_cast<uint32_t>(gu) >= static_cast<uint32_t>(gc.nu)) continue;
+        // Value of one fixed-point unit, 2^(e - 31) (unused on the FP32 path).
+        float inv_s = 0.0f;
+        if (!fp32_path) {
+          int e;
+          frexpf(1.01f * static_cast<float>(kcount[sl]) * __uint_as_float(mbits[sl]), &e);
+          inv_s = ldexpf(1.0f, e - 31);
+        }
         float* qs = q + s * vstride + gu;
         for (int32_t r = sr; r < tv; r += rstep) {
           const int32_t at = sl * slot + sc * tvp + r;
-          const float ex = atile[at];
+          const float ex = fp32_path ? __int_as_float(atile[at]) : static_cast<float>(atile[at]) * inv_s;
           const int32_t gr = bvs[s].org_v + r;
           if (ex != 0.0f && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv))
             unsafeAtomicAdd(qs + static_cast<int64_t>(gr) * gc.nu, ex);
           if (MIRROR) {
-            const float ey = mtile[at];
+            const float ey = fp32_path ? __int_as_float(mtile[at]) : static_cast<float>(mtile[at]) * inv_s;
             const int32_t gm = gc.mirror_g - gr;
             if (ey != 0.0f && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv))
               unsafeAtomicAdd(qs + static_cast<int64_t>(gm) * gc.nu, ey);
@@ -270,13 +387,13 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
       vsplit = (kFpSplitTarget + static_cast<int64_t>(nwg) - 1) / static_cast<int64_t>(nwg);
     vsplit = std::max<int64_t>(1, std::min<int64_t>(vsplit, vb.nviews));
     const dim3 grid(static_cast<uint32_t>(nwg), static_cast<uint32_t>(vsplit));
-    // Adjoint tile: one more column than the back-projection tile, one FP32
-    // word per pixel and plane (main, plus mirror for mirrored runs).
+    // Adjoint tile: one more column than the back-projection tile, one
+    // 32-bit word per pixel and plane (main, plus mirror for mirrored runs).
     // The host sizes the back-projection tile at 16 (mirrored) or 8 (plain)
     // bytes per entry, so at least one view's tile always fits.
     TileShape tf = ts;
     const int64_t per_view =
-        static_cast<int64_t>(ts.tu + 1) * ts.tvp * sizeof(float) * (run.mirror ? 2 : 1);
+        static_cast<int64_t>(ts.tu + 1) * ts.tvp * sizeof(int) * (run.mirror ? 2 : 1);
     tf.vc = static_cast<int32_t>(std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view));
     if (tf.vc < 1) return static_cast<int>(hipErrorInvalidValue);
     const size_t lds = static_cast<size_t>(tf.vc) * per_view;

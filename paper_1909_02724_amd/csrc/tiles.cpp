@@ -18,7 +18,7 @@ namespace fdk {
 // spread dz the rows span at most kv ((bz - 1) / zmin + |k - cz| dz / zmin^2).
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots,
-                     bool direct, bool cells) {
+                     bool direct) {
   TileShape ts{};
   ts.rot_a = 1;
   ts.rot_b = 4;
@@ -43,16 +43,13 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   // origin margin one pixel, FP32 column arithmetic up to one more.
   ts.tu = static_cast<int32_t>(std::ceil(wu)) + 4;
   ts.tv = static_cast<int32_t>(std::ceil(wv)) + 5;
-  // Odd pitch: 16 neighbouring columns hit distinct LDS banks.
-  const int32_t nent = cells ? ts.tv - 1 : ts.tv;
-  ts.tvp = nent | 1;
+  ts.tvp = ts.tv | 1;  // odd pitch: 16 neighbouring columns hit distinct LDS banks
   if (ts.tu + 1 > kBrickThreads) return ts;  // staging and the adjoint's flush: a thread per column
   ts.rstep = kBrickThreads / ts.tu;
-  ts.rows = (nent + ts.rstep - 1) / ts.rstep;
+  ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
   const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * entry_bytes;
   int64_t vc = std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);
-  // A thread's cells need one more row than it has cells.
-  vc = std::min<int64_t>(vc, slots / (cells ? ts.rows + 1 : ts.rows));
+  vc = std::min<int64_t>(vc, slots / ts.rows);
   ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
   return ts;
 }

@@ -1,22 +1,30 @@
 """Precision of the adjoint (the forward projector, the transpose of Alg. 2
 computed as Alg. 4 with Alg. 3's bilinear taps) on inputs that stress how it
-accumulates:
+accumulates. The tiled adjoint sums each brick's splats in LDS as 32-bit
+fixed point, with a power-of-two unit of about 2^-31 of the brick's largest
+possible splat times the pixels' overlap; bricks holding a NaN or an
+infinity, or more than 1 % of non-zero voxels below 2^-13 of their largest
+magnitude, sum in FP32 instead. So:
 
-* volumes whose values span eight decades inside every 16^3 brick (one
-  large voxel per brick over a unit or a tiny background; log-uniform
-  magnitudes with random signs), against the FP64 oracle (rel-L2) and, pixel
-  by pixel, against the superposition of the same projector applied to the
-  large and the small parts separately. The superposition isolates the
-  accumulation: all three projections use identical taps and weights, so
-  they differ only by how each pixel's contributions are summed, and that
-  difference must stay below 1e-5 of the pixel's sum of |contributions|.
-  (Compared with the oracle pixel by pixel, FP32 coordinates alone move a
-  large voxel's weight on a footprint edge by ~1e-6, which across eight
-  decades exceeds 1e-5 of a small neighbour; the oracle comparison is
-  therefore the rel-L2 one.)
+* wide-range volumes (values over eight decades inside every 16^3 brick:
+  one large voxel per brick over a unit or a tiny background; log-uniform
+  magnitudes with random signs) take the FP32 path. Against the FP64
+  oracle they match in rel-L2; pixel by pixel, the superposition of the
+  same projector applied to the large and the small parts separately
+  isolates the accumulation (all three projections use identical taps and
+  weights, and all three volumes are wide-range, so all take the FP32
+  path): each pixel's discrepancy must stay below 1e-5 of the pixel's sum
+  of |contributions|. (Compared with the oracle pixel by pixel, FP32
+  coordinates alone move a large voxel's weight on a footprint edge by
+  ~1e-6, which across eight decades exceeds 1e-5 of a small neighbour; the
+  oracle comparison is therefore the rel-L2 one.)
+* ordinary volumes take the fixed-point path, whose error is bounded
+  relative to the brick's largest splats, not each pixel's own sum: the
+  superposition of two disjoint halves holds to 1e-6 of the largest pixel.
 * non-finite inputs: a NaN or an infinity reaches exactly the pixels its
   voxel touches, and every other pixel is unaffected;
-* magnitudes near the bottom of the FP32 range.
+* magnitudes near the bottom of the FP32 range (the power-of-two unit
+  cannot overflow).
 """
 import numpy as np
 import pytest
@@ -54,28 +62,37 @@ def fp(x, g, ang, direct=False):
 
 
 def split_volume(kind, g, seed):
-    """(large part, small part) of a test volume, as float32 arrays."""
+    """(large part, small part) of a wide-range test volume, as float32
+    arrays. Each part also carries, at 3 % of the voxels (disjoint sets for
+    the two parts), values 1e-13 of its largest magnitude, so that every
+    brick of both parts and of their sum is wide-range."""
     rng = np.random.default_rng(seed)
     shape = (g.nz, g.ny, g.nx)
     if kind == "loguniform":
         x = (10.0 ** rng.uniform(-4.0, 4.0, shape)) * rng.choice([-1.0, 1.0], shape)
         x = x.astype(np.float32)
         big = np.abs(x) >= 1.0
-        return np.where(big, x, 0).astype(np.float32), np.where(big, 0, x).astype(np.float32)
-    background = 1.0 if kind == "spike" else 1e-4
-    small = np.full(shape, background, np.float32)
-    large = np.zeros(shape, np.float32)
-    # One voxel of 1e4 per 16^3 block of the volume (the kernels' bricks are
-    # 16 x 16 columns of 16 or 32 slices), at a seeded place inside it.
-    for k0 in range(0, g.nz, 16):
-        for j0 in range(0, g.ny, 16):
-            for i0 in range(0, g.nx, 16):
-                k = min(k0 + rng.integers(16), g.nz - 1)
-                j = min(j0 + rng.integers(16), g.ny - 1)
-                i = min(i0 + rng.integers(16), g.nx - 1)
-                large[k, j, i] = 1e4
-                small[k, j, i] = 0.0
-    return large, small
+        large, small = np.where(big, x, 0).astype(np.float32), np.where(big, 0, x).astype(np.float32)
+    else:
+        background = 1.0 if kind == "spike" else 1e-4
+        small = np.full(shape, background, np.float32)
+        large = np.zeros(shape, np.float32)
+        # One voxel of 1e4 per 16^3 block of the volume (the kernels' bricks
+        # are 16 x 16 columns of 16 or 32 slices), at a seeded place inside it.
+        for k0 in range(0, g.nz, 16):
+            for j0 in range(0, g.ny, 16):
+                for i0 in range(0, g.nx, 16):
+                    k = min(k0 + rng.integers(16), g.nz - 1)
+                    j = min(j0 + rng.integers(16), g.ny - 1)
+                    i = min(i0 + rng.integers(16), g.nx - 1)
+                    large[k, j, i] = 1e4
+                    small[k, j, i] = 0.0
+    pick = rng.uniform(0.0, 1.0, shape)
+    seeds_l, seeds_s = pick < 0.03, (pick >= 0.03) & (pick < 0.06)
+    sign = rng.choice([-1.0, 1.0], shape)
+    large = np.where(seeds_l & (large == 0), 1e-13 * np.abs(large).max() * sign, large)
+    small = np.where(seeds_s, 1e-13 * np.abs(small).max() * sign, small)
+    return large.astype(np.float32), small.astype(np.float32)
 
 
 @pytest.mark.parametrize("direct", [False, True], ids=["tiled", "direct"])
@@ -99,6 +116,30 @@ def test_adjoint_high_dynamic_range(name, kind, direct):
              f"F|x| = {worst:.3e}, pixels over 1e-5: {int(np.sum(excess > 0))}")
     assert err <= 1e-5
     assert np.all(excess <= 0.0)
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_adjoint_fixed_point_bound(name):
+    """Ordinary volumes (U(0.5, 1.5), no wide-range brick) take the 32-bit
+    fixed-point tile: exact integer sums of splats rounded to a unit of
+    about 2^-31 of the brick's largest splat times the overlap. Splitting the
+    volume into two disjoint random halves changes each brick's scale, so
+    the superposition measures the rounding: bounded by 1e-6 of the largest
+    pixel, and the rel-L2 against the oracle by 1e-5."""
+    g = GEOMS[name]
+    ang = synth.angles(37, start=0.2)
+    rng = np.random.default_rng(77)
+    x = rng.uniform(0.5, 1.5, (g.nz, g.ny, g.nx)).astype(np.float32)
+    half = rng.uniform(0.0, 1.0, x.shape) < 0.5
+    xa, xb = np.where(half, x, 0).astype(np.float32), np.where(half, 0, x).astype(np.float32)
+    f_x, f_a, f_b = fp(x, g, ang), fp(xa, g, ang), fp(xb, g, ang)
+    ref = oracle.forward_project(g, ang, x.astype(np.float64), scale=0.9)
+    err = rel_l2(f_x, ref)
+    sup = float(np.max(np.abs(f_x - f_a - f_b)) / np.max(np.abs(f_x)))
+    announce(f"adjoint fixed point {name}: rel-L2 vs oracle {err:.3e}; "
+             f"max |F x - F x_a - F x_b| / max F x = {sup:.3e}")
+    assert err <= 1e-5
+    assert sup <= 1e-6
 
 
 @pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf], ids=["nan", "inf", "-inf"])

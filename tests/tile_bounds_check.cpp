@@ -44,10 +44,7 @@ void check_run(const fdk_geometry& g, const fdk::GeoConst& gc, const fdk::SliceR
   using namespace fdk;
   const bool mirror = run.mirror != 0;
   const int32_t bz = mirror ? kBrickZ : kPlainBrickZ;
-  // Mirrored runs: the back-projector's cell tile (the adjoint sizes its own
-  // tile from the same tu and tv).
-  const TileShape ts = mirror ? tile_shape(&g, gc, run, vb, bz, kCellBytes, kPrefetchSlots, false,
-                                           true)
+  const TileShape ts = mirror ? tile_shape(&g, gc, run, vb, bz, kTileEntryBytes, kPrefetchSlots, false)
                               : tile_shape(&g, gc, run, vb, bz, kPlainEntryBytes,
                                            kPlainPrefetchSlots, false);
   ++st->geometries;
@@ -88,7 +85,7 @@ void check_run(const fdk_geometry& g, const fdk::GeoConst& gc, const fdk::SliceR
               // tile has tu + 1 columns for the same taps.)
               const int col_slack = ts.tu - 1 - static_cast<int>(c.nu);
               // v grows with the slot: the last voxel reads the highest row,
-              // nvb + dn + 1 < tv (its cell nvb + dn is below tv - 1).
+              // nvb + dn + 1 < tv.
               uint32_t dn = 0;
               float fr = 0.0f;
               voxel_row_off(c.fvb, c.dvk, bz - 1, &dn, &fr);
