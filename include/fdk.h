@@ -221,6 +221,24 @@ FDK_API fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int3
                                       float lambda, uint32_t flags, float* proj_tmp,
                                       float* vol_tmp, void* stream);
 
+/* fdk_sirt_iteration without workspace arguments, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): proj_tmp and vol_tmp come from a
+ * static per-GPU array of 2^24 floats (64 MiB) that the library holds from
+ * its load until the process ends, so the call allocates nothing. The
+ * projections of the view range, rounded up to 64 floats, plus the slab's
+ * voxels must fit that array, else FDK_ERR_INVALID_ARG. Every call on one
+ * GPU shares its array: calls that overlap on a GPU (on different streams
+ * or threads) race and must be ordered by the caller. Other arguments and
+ * errors: as fdk_sirt_iteration, plus FDK_ERR_HIP if the array's device
+ * address cannot be obtained. */
+FDK_API fdk_status fdk_sirt_iteration_noalloc(const fdk_geometry* g, int32_t view0,
+                                              int32_t nviews, const float* p,
+                                              const float* row_inv, const float* col_inv,
+                                              float* x, int32_t z0, int32_t nz_local,
+                                              fdk_slab_kind slab, float lambda, uint32_t flags,
+                                              void* stream);
+
 /* One MLEM iteration (maximum-likelihood expectation maximisation, Shepp
  * and Vardi 1982; another of the iterative methods the paper names as users
  * of the back-projection) on x (device FP32 slab, updated in place) for

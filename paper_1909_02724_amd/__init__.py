@@ -21,7 +21,8 @@ import torch
 __all__ = [
     "Geometry", "FDKError", "lib", "backproject", "forward_project", "filter",
     "filter_adjoint", "slab_rows", "fdk_scale", "FDKBackprojection", "fdk_backprojection",
-    "FDKReconstruction", "fdk_reconstruction", "sirt_weights", "sirt_iteration", "sirt",
+    "FDKReconstruction", "fdk_reconstruction", "sirt_weights", "sirt_iteration",
+    "sirt_iteration_noalloc", "sirt",
     "mlem_iteration", "mlem",
 ]
 
@@ -116,6 +117,10 @@ def lib():
                                          C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int,
                                          C.c_float, C.c_uint32, C.c_void_p, C.c_void_p,
                                          C.c_void_p]
+        L.fdk_sirt_iteration_noalloc.restype = C.c_int
+        L.fdk_sirt_iteration_noalloc.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                                 C.c_int, C.c_float, C.c_uint32, C.c_void_p]
         L.fdk_mlem_iteration.restype = C.c_int
         L.fdk_mlem_iteration.argtypes = [P, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_int32, C.c_int32, C.c_int, C.c_void_p,
@@ -412,6 +417,24 @@ def sirt_iteration(x, p, row_inv, col_inv, geom, angles, *, view0: int = 0, z0: 
                                     C.c_void_p(x.data_ptr()), z0, nzl, sk, float(lam),
                                     FDK_NONNEG if nonneg else 0, C.c_void_p(proj_tmp.data_ptr()),
                                     C.c_void_p(vol_tmp.data_ptr()), _stream(x)))
+    return x
+
+
+def sirt_iteration_noalloc(x, p, row_inv, col_inv, geom, angles, *, view0: int = 0, z0: int = 0,
+                           slab: str = "contiguous", lam: float = 1.0, nonneg: bool = False):
+    """sirt_iteration with the library's static per-GPU workspace (64 MiB):
+    allocates nothing, for callers that cannot; calls that overlap on one
+    GPU race."""
+    z0, nzl, sk = _slab(geom, z0, x.shape[0], slab)
+    _f32_dev(x, (nzl, geom.ny, geom.nx), "x")
+    _f32_dev(p, (p.shape[0], geom.nv, geom.nu), "p")
+    _f32_dev(row_inv, p.shape, "row_inv")
+    _f32_dev(col_inv, x.shape, "col_inv")
+    cg, _keep = _cgeom(geom, angles)
+    _check(lib().fdk_sirt_iteration_noalloc(
+        C.byref(cg), view0, p.shape[0], C.c_void_p(p.data_ptr()), C.c_void_p(row_inv.data_ptr()),
+        C.c_void_p(col_inv.data_ptr()), C.c_void_p(x.data_ptr()), z0, nzl, sk, float(lam),
+        FDK_NONNEG if nonneg else 0, _stream(x)))
     return x
 
 

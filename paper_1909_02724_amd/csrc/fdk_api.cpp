@@ -515,6 +515,36 @@ fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int32_t nvie
   return ok();
 }
 
+fdk_status fdk_sirt_iteration_noalloc(const fdk_geometry* g, int32_t view0, int32_t nviews,
+                                      const float* p, const float* row_inv, const float* col_inv,
+                                      float* x, int32_t z0, int32_t nz_local, fdk_slab_kind slab,
+                                      float lambda, uint32_t flags, void* stream) {
+  fdk_status st = check_geometry(g);
+  if (st) return st;
+  if ((st = check_views(g, view0, nviews))) return st;
+  if (nviews <= 0) return fail(FDK_ERR_INVALID_ARG, "SIRT needs at least one view");
+  if (!p || !row_inv || !col_inv || !x) return fail(FDK_ERR_INVALID_ARG, "SIRT buffer pointer is NULL");
+  if (!std::isfinite(lambda)) return fail(FDK_ERR_INVALID_ARG, "lambda is not finite");
+  if (flags & ~FDK_NONNEG) return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  const fdk::GeoConst gc = make_geo(g);
+  Slab sl;
+  if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
+  // Workspace: the projections' residual, then (256-byte aligned) the
+  // slab's back-projection, both in the per-GPU static array.
+  const int64_t nproj = (int64_t)nviews * g->nu * g->nv;
+  const int64_t nvox = slab_voxels(g, nz_local);
+  const int64_t vol_off = (nproj + 63) / 64 * 64;
+  if (vol_off + nvox > fdk::kStaticScratchFloats)
+    return fail(FDK_ERR_INVALID_ARG,
+                "workspace of %lld projection and %lld slab values exceeds the static %lld floats",
+                (long long)nproj, (long long)nvox, (long long)fdk::kStaticScratchFloats);
+  float* ws = nullptr;
+  if (int e = fdk::static_scratch(&ws))
+    return fail(FDK_ERR_HIP, "static workspace lookup failed: HIP error %d", e);
+  return fdk_sirt_iteration(g, view0, nviews, p, row_inv, col_inv, x, z0, nz_local, slab, lambda,
+                            flags, ws, ws + vol_off, stream);
+}
+
 fdk_status fdk_mlem_iteration(const fdk_geometry* g, int32_t view0, int32_t nviews, const float* p,
                               const float* col_inv, float* x, int32_t z0, int32_t nz_local,
                               fdk_slab_kind slab, float* proj_tmp, float* vol_tmp, void* stream) {

@@ -23,6 +23,11 @@ int launch_mlem_ratio(const float* p, float* r, int64_t n, float floor_rel, uint
                       void* stream);
 // MLEM: x <- x * col_inv * b.
 int launch_mlem_update(float* x, const float* col_inv, const float* b, int64_t n, void* stream);
+// Per-GPU static workspace of the entry points that allocate nothing
+// (sirt.hip): kStaticScratchFloats floats (64 MiB). static_scratch gives its
+// device address on the current device (looked up once per device).
+constexpr int64_t kStaticScratchFloats = int64_t{1} << 24;
+int static_scratch(float** out);
 // Filter rows [v0, v0 + band) of nviews views; row m of the launch is view
 // m / band, detector row v0 + m % band; view strides in elements.
 struct RowBand {

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "ops_internal.h"
 
@@ -134,6 +135,35 @@ int launch_mlem_ratio(const float* p, float* r, int64_t n, float floor_rel, uint
   hipLaunchKernelGGL(mlem_ratio_kernel, ew_grid(n), dim3(kEwThreads), 0, st, p, r, n, maxbits,
                      floor_rel);
   return static_cast<int>(hipGetLastError());
+}
+
+// Workspace of the entry points that allocate nothing: one array per GPU,
+// held from the library's load until the process ends. Host code never
+// uses the array's name as an address (on the host it is only a stand-in):
+// the device address comes from hipGetSymbolAddress, once per device, with
+// that device current.
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+int static_scratch(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return static_cast<int>(e);
+  if (dev < 0 || dev >= kMaxScratchDevices) return static_cast<int>(hipErrorInvalidDevice);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return static_cast<int>(e);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<float*>(g_scratch_ptr[dev]);
+  return 0;
 }
 
 int launch_mlem_update(float* x, const float* col_inv, const float* b, int64_t n, void* stream) {

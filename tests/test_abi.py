@@ -226,6 +226,28 @@ def test_sirt_validation():
     assert "flags" in L.fdk_last_error().decode()
 
 
+def test_sirt_noalloc_validation():
+    """The static-workspace SIRT iteration refuses, on the host, inputs whose
+    workspace (projections rounded up to 64 floats, plus the slab) exceeds
+    its 2^24 floats, and otherwise validates like fdk_sirt_iteration."""
+    L = fdk.lib()
+    it = L.fdk_sirt_iteration_noalloc
+    A, B_, C_, D_ = (C.c_void_p(0x1000 * k) for k in (1, 2, 3, 4))
+    cg, keep = fdk._cgeom(GOOD, ANG)
+    assert it(C.byref(cg), 0, 0, A, B_, C_, D_, 0, 8, 0, 1.0, 0, None) == 1      # no views
+    assert it(C.byref(cg), 0, 4, A, B_, C_, D_, 0, 0, 0, 1.0, 0, None) == 1      # empty slab
+    big = synth.Geom(nx=256, ny=256, nz=256, nu=256, nv=256, sod=2000.0, sdd=4000.0)
+    ang = synth.angles(4)
+    cgb, keepb = fdk._cgeom(big, ang)
+    # 4 x 256^2 projection values + 256^3 voxels = 2^24 + 2^18 > 2^24
+    assert it(C.byref(cgb), 0, 4, A, B_, C_, D_, 0, 256, 0, 1.0, 0, None) == 1
+    assert "static" in L.fdk_last_error().decode()
+    # a slab of 255 slices fits exactly: (2^18 + 255 * 2^16) <= 2^24, so the
+    # size check passes and the next check (the NaN lambda) fails instead
+    assert it(C.byref(cgb), 0, 4, A, B_, C_, D_, 0, 252, 0, float("nan"), 0, None) == 1
+    assert "lambda" in L.fdk_last_error().decode()
+
+
 def test_mlem_validation():
     L = fdk.lib()
     cg, keep = fdk._cgeom(GOOD, ANG)
