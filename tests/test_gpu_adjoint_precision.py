@@ -12,8 +12,8 @@ magnitude, sum in FP32 instead. So:
   oracle they match in rel-L2; pixel by pixel, the superposition of the
   same projector applied to the large and the small parts separately
   isolates the accumulation (all three projections use identical taps and
-  weights, and all three volumes are wide-range, so all take the FP32
-  path): each pixel's discrepancy must stay below 1e-5 of the pixel's sum
+  weights, and every brick of all three volumes is wide-range, so all take
+  the FP32 path): each pixel's discrepancy must stay below 1e-5 of the pixel's sum
   of |contributions|. (Compared with the oracle pixel by pixel, FP32
   coordinates alone move a large voxel's weight on a footprint edge by
   ~1e-6, which across eight decades exceeds 1e-5 of a small neighbour; the
@@ -63,9 +63,9 @@ def fp(x, g, ang, direct=False):
 
 def split_volume(kind, g, seed):
     """(large part, small part) of a wide-range test volume, as float32
-    arrays. Each part also carries, at 3 % of the voxels (disjoint sets for
-    the two parts), values 1e-13 of its largest magnitude, so that every
-    brick of both parts and of their sum is wide-range."""
+    arrays. Each part also carries, at 1 in 32 voxels (disjoint sets for the
+    two parts), values 1e-13 of its largest magnitude, so that every brick
+    of both parts and of their sum is wide-range."""
     rng = np.random.default_rng(seed)
     shape = (g.nz, g.ny, g.nx)
     if kind == "loguniform":
@@ -87,8 +87,11 @@ def split_volume(kind, g, seed):
                     i = min(i0 + rng.integers(16), g.nx - 1)
                     large[k, j, i] = 1e4
                     small[k, j, i] = 0.0
-    pick = rng.uniform(0.0, 1.0, shape)
-    seeds_l, seeds_s = pick < 0.03, (pick >= 0.03) & (pick < 0.06)
+    # Seed voxels on a lattice (1 in 32 for each part, disjoint), so that
+    # even the volume's partial edge bricks hold more than 1 % of them.
+    kk, jj, ii = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    lattice = (ii + 7 * jj + 13 * kk) % 32
+    seeds_l, seeds_s = lattice == 0, lattice == 16
     sign = rng.choice([-1.0, 1.0], shape)
     large = np.where(seeds_l & (large == 0), 1e-13 * np.abs(large).max() * sign, large)
     small = np.where(seeds_s, 1e-13 * np.abs(small).max() * sign, small)
