@@ -31,19 +31,23 @@ constexpr uint32_t kBadCol = 0x40000000u;  // pushes a buffer offset out of rang
 constexpr uint32_t kBadRow = 0x80000000u;
 constexpr int kBufferWord3 = 0x00020000;   // raw buffer descriptor, gfx9 family
 
+// Raw buffer load at vector offset off plus scalar (wave-uniform) offset soff.
 template <typename T>
-__device__ __forceinline__ uint32_t buf_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t off);
+__device__ __forceinline__ uint32_t buf_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff);
 template <>
-__device__ __forceinline__ uint32_t buf_load_raw<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+__device__ __forceinline__ uint32_t buf_load_raw<float>(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                        uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0);
 }
 template <>
-__device__ __forceinline__ uint32_t buf_load_raw<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+__device__ __forceinline__ uint32_t buf_load_raw<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                        uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
 }
 template <>
-__device__ __forceinline__ uint32_t buf_load_raw<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+__device__ __forceinline__ uint32_t buf_load_raw<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                         uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
 }
 template <typename T>
 __device__ __forceinline__ float raw_to_f32(uint32_t bits);
@@ -81,7 +85,20 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   const int32_t i_lo = bx * kBrickX, j_lo = by * kBrickY;
   const int32_t i_hi = min(i_lo + kBrickX - 1, gc.nx - 1);
   const int32_t j_hi = min(j_lo + kBrickY - 1, gc.ny - 1);
-  const int32_t tx0 = tid % kBrickX, ty0 = tid / kBrickX;
+  // Voxel column of the thread in the brick. The mirrored tiled variant reads
+  // 16-byte tile entries, which the LDS serves 16 lanes at a time: in each
+  // half wave, the lanes whose quad (lane / 4) has even bit parity, then
+  // those with odd parity. Each such group takes a 4 x 4 patch of columns
+  // (its quads the patch's rows), so its reads span a few tile columns and,
+  // with the column pitch at 7 or 9 mod 16, fall in distinct banks. A wave
+  // still covers 16 x 4 columns, so the volume writes stay coalesced.
+  int32_t tx0 = tid % kBrickX, ty0 = tid / kBrickX;
+  if constexpr (MIRROR && TILED) {
+    const int32_t lane = tid & 63, quad = (lane >> 2) & 7;
+    const int32_t par = __builtin_popcount(quad) & 1;
+    tx0 = 4 * (2 * (lane >> 5) + par) + (lane & 3);
+    ty0 = 4 * (tid >> 6) + (quad >> 1);
+  }
   const bool owner = (i_lo + tx0 <= i_hi) && (j_lo + ty0 <= j_hi);
   const int32_t i = min(i_lo + tx0, i_hi), j = min(j_lo + ty0, j_hi);
   const float txf = static_cast<float>(i - i_lo), tyf = static_cast<float>(j - j_lo);
@@ -119,14 +136,32 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     constexpr int NSLOT = MIRROR ? kPrefetchSlots : kPlainPrefetchSlots;
     uint4 pre[NSLOT];
 
+    // Per-lane parts of the staging offsets, fixed for the launch: column sc
+    // and first row sr relative to the tile origin, main rows downwards in
+    // the buffer and mirror rows upwards. Lanes that stage nothing start
+    // from kBadRow, which a view's base offset and the row steps (a few MB
+    // at most) keep out of range, so their loads return zero without a
+    // fetch and need no select.
+    const uint32_t t_main =
+        stager ? static_cast<uint32_t>(sr) * row_es + static_cast<uint32_t>(sc) * es : kBadRow;
+    const uint32_t t_mir =
+        stager ? static_cast<uint32_t>(sc) * es - static_cast<uint32_t>(sr) * row_es : kBadRow;
+    const uint32_t step = static_cast<uint32_t>(rstep) * row_es;
+
     // Issue the loads of views [s0, s0 + nvc) into pre[]: raw (q(u), q(u+1))
-    // for the row and for its mirror row. Views whose tile lies on the
-    // detector skip the range checks.
+    // for the row and for its mirror row. A thread loads rows sr + rr rstep
+    // for every pass rr, also those at or beyond tv (the store drops them),
+    // so the loads need no row test. Views whose tile lies on the detector
+    // skip the range checks: rows past the tile may leave the detector, but
+    // their offsets then fall out of the buffer's range (below zero they
+    // wrap), which reads zero.
     auto load_stage = [&](int32_t s0, int32_t nvc) {
+      // Uniform, but the compiler may keep it in a vector register and then
+      // treat every branch on it as divergent.
+      nvc = __builtin_amdgcn_readfirstlane(nvc);
       int32_t sl = 0, rr = 0;
-      int32_t org_v = 0, inside = 0;
-      uint32_t c0 = 0, c1 = 0, off = 0, offm = 0;
-      const uint32_t step = static_cast<uint32_t>(rstep) * row_es;
+      int32_t org_u = 0, org_v = 0, inside = 0;
+      uint32_t off = 0, offm = 0;
 #pragma unroll
       for (int m = 0; m < NSLOT; ++m) {
         if (sl < nvc) {
@@ -137,35 +172,38 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
               const_cast<T*>(q + (s0 + sl) * vstride), 0, nrec, kBufferWord3);
           if (rr == 0) {  // uniform: new view
             const int32_t s = s0 + sl;
-            const int32_t gu = bvs[s].org_u + sc;
-            org_v = bvs[s].org_v;
+            org_u = __builtin_amdgcn_readfirstlane(bvs[s].org_u);
+            org_v = __builtin_amdgcn_readfirstlane(bvs[s].org_v);
             inside = __builtin_amdgcn_readfirstlane(bvs[s].inside);
-            c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
-                     ? static_cast<uint32_t>(gu) * es : kBadCol;
-            c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
-                     ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
-            off = static_cast<uint32_t>(org_v + sr) * row_es + c0;
-            offm = static_cast<uint32_t>(MIRROR ? gc.mirror_g - org_v - sr : 0) * row_es + c0;
+            off = t_main + (static_cast<uint32_t>(org_v) * row_es + static_cast<uint32_t>(org_u) * es);
+            offm = t_mir + (static_cast<uint32_t>(MIRROR ? gc.mirror_g - org_v : 0) * row_es +
+                            static_cast<uint32_t>(org_u) * es);
           }
           // Only the offsets depend on the branch: the loads themselves are
           // issued in common code, unconditionally (uniform control flow),
-          // so nothing waits for them until the tile is written. A lane with
-          // no row here reads at an out-of-range offset, which returns zero
-          // without a fetch. Views whose tile lies on the detector just step
-          // the row offsets.
-          const int32_t r = sr + rr * rstep;
-          const bool on = stager && r < tv;
+          // so nothing waits for them until the tile is written.
           uint32_t o0, o1, m0, m1;
           if (inside) {
-            o0 = on ? off : kBadRow;
-            o1 = o0 + es;
-            m0 = on ? offm : kBadRow;
-            m1 = m0 + es;
+            // q(u + 1) at the next element: the tile's last column plus one
+            // is on the detector, so it never crosses a row end.
+            const uint32_t rs = static_cast<uint32_t>(rr) * step;
+            o0 = off + rs;
+            o1 = off + (rs + es);
+            m0 = offm - rs;
+            m1 = offm + (es - rs);
           } else {
-            const int32_t gr = org_v + r, gm = MIRROR ? gc.mirror_g - gr : -1;
-            const uint32_t ro = on && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
+            const int32_t gu = org_u + sc;
+            const uint32_t c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
+                                    ? static_cast<uint32_t>(gu) * es : kBadCol;
+            const uint32_t c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
+                                    ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
+            // (The uniform part is summed first: hoisted out of the stage
+            // loop, per-slot lane values would be kept in spilled registers.)
+            const int32_t gr = __builtin_amdgcn_readfirstlane(org_v + rr * rstep) + sr;
+            const int32_t gm = MIRROR ? gc.mirror_g - gr : -1;
+            const uint32_t ro = stager && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
                                     ? static_cast<uint32_t>(gr) * row_es : kBadRow;
-            const uint32_t rm = on && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
+            const uint32_t rm = stager && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
                                     ? static_cast<uint32_t>(gm) * row_es : kBadRow;
             o0 = ro + c0;
             o1 = ro + c1;
@@ -173,16 +211,14 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
             m1 = rm + c1;
           }
           uint4 p;
-          p.x = buf_load_raw<T>(rsrc, o0);
-          p.y = buf_load_raw<T>(rsrc, o1);
+          p.x = buf_load_raw<T>(rsrc, o0, 0);
+          p.y = buf_load_raw<T>(rsrc, o1, 0);
           if (MIRROR) {
-            p.z = buf_load_raw<T>(rsrc, m0);
-            p.w = buf_load_raw<T>(rsrc, m1);
+            p.z = buf_load_raw<T>(rsrc, m0, 0);
+            p.w = buf_load_raw<T>(rsrc, m1, 0);
           }
           if (!MIRROR) p.z = p.w = 0u;
           pre[m] = p;
-          off += step;
-          offm -= step;
         }
         if (++rr == rows) {
           rr = 0;
@@ -191,20 +227,24 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
       }
     };
 
+    // Tile entry (sc, sr + rr rstep) of each view. Only the last pass can
+    // reach rows at or beyond tv, whose loads are discarded here.
+    const uint32_t lds_lane = static_cast<uint32_t>(sc * tvp + sr);
+    const bool last_ok = stager && sr + (rows - 1) * rstep < tv;
     auto store_stage = [&](int32_t nvc) {
+      nvc = __builtin_amdgcn_readfirstlane(nvc);
       int32_t sl = 0, rr = 0;
 #pragma unroll
       for (int m = 0; m < NSLOT; ++m) {
         if (sl < nvc) {
-          const int32_t r = sr + rr * rstep;
-          if (stager && r < tv) {
+          if (rr == rows - 1 ? last_ok : stager) {
+            const uint32_t at = lds_lane + static_cast<uint32_t>(sl * slot_entries + rr * rstep);
             const float a0 = raw_to_f32<T>(pre[m].x), a1 = raw_to_f32<T>(pre[m].y);
             if constexpr (MIRROR) {
               const float b0 = raw_to_f32<T>(pre[m].z), b1 = raw_to_f32<T>(pre[m].w);
-              tile[sl * slot_entries + sc * tvp + r] = make_float4(a0, a1 - a0, b0, b1 - b0);
+              tile[at] = make_float4(a0, a1 - a0, b0, b1 - b0);
             } else {
-              reinterpret_cast<float2*>(tile)[sl * slot_entries + sc * tvp + r] =
-                  make_float2(a0, a1 - a0);
+              reinterpret_cast<float2*>(tile)[at] = make_float2(a0, a1 - a0);
             }
           }
         }

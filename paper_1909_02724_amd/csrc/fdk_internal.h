@@ -77,10 +77,11 @@ struct TileShape {
 // exceeds the LDS or prefetch budget, or the caller asks for the direct
 // variant (FDK_DIRECT).
 // bz: slices per brick; entry_bytes: LDS bytes per tile entry; slots: tile
-// entries a thread prefetches per stage.
+// entries a thread prefetches per stage; read_pitch: pad the column pitch for
+// the mirrored back-projector's conflict-free entry reads.
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots,
-                     bool direct);
+                     bool direct, bool read_pitch = false);
 // Plain (unmirrored) back-projection runs: 32 slices per brick, the tile
 // holding (q, dq/du) of the main rows only; a prefetch slot holds one row's
 // pair instead of two, so twice as many fit the same registers.

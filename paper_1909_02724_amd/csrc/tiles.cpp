@@ -18,7 +18,7 @@ namespace fdk {
 // spread dz the rows span at most kv ((bz - 1) / zmin + |k - cz| dz / zmin^2).
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots,
-                     bool direct) {
+                     bool direct, bool read_pitch) {
   TileShape ts{};
   ts.rot_a = 1;
   ts.rot_b = 4;
@@ -44,6 +44,14 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   ts.tu = static_cast<int32_t>(std::ceil(wu)) + 4;
   ts.tv = static_cast<int32_t>(std::ceil(wv)) + 5;
   ts.tvp = ts.tv | 1;  // odd pitch: 16 neighbouring columns hit distinct LDS banks
+  if (read_pitch) {
+    // The back-projector's 16-byte entry reads are served 16 lanes at a
+    // time over 64 four-byte banks, and those 16 lanes cover a 4 x 4 patch
+    // of voxel columns: a few tile columns, rows n and n + 1. With the pitch
+    // at 7 or 9 mod 16, entries nu tvp + n of two such lanes share a bank
+    // only if their columns are 7 or more apart.
+    while (ts.tvp % 16 != 7 && ts.tvp % 16 != 9) ts.tvp += 2;
+  }
   if (ts.tu + 1 > kBrickThreads) return ts;  // staging and the adjoint's flush: a thread per column
   ts.rstep = kBrickThreads / ts.tu;
   ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;

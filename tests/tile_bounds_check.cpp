@@ -44,7 +44,7 @@ void check_run(const fdk_geometry& g, const fdk::GeoConst& gc, const fdk::SliceR
   using namespace fdk;
   const bool mirror = run.mirror != 0;
   const int32_t bz = mirror ? kBrickZ : kPlainBrickZ;
-  const TileShape ts = mirror ? tile_shape(&g, gc, run, vb, bz, kTileEntryBytes, kPrefetchSlots, false)
+  const TileShape ts = mirror ? tile_shape(&g, gc, run, vb, bz, kTileEntryBytes, kPrefetchSlots, false, true)
                               : tile_shape(&g, gc, run, vb, bz, kPlainEntryBytes,
                                            kPlainPrefetchSlots, false);
   ++st->geometries;
