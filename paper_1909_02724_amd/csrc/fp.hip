@@ -17,9 +17,11 @@ namespace {
 
 // Tiled variant: per view, the brick's splats accumulate in LDS tiles with
 // the back-projector's transposed layout (one more column, for the u + 1
-// taps), one plane for main rows and one for mirror rows, as 32-bit fixed
-// point (FP32 for bricks that need it); the tiles are then added to the
-// projection with one global atomic per non-zero pixel. Direct variant: global atomics per tap.
+// taps) as 32-bit fixed point, a row's and its mirror row's sums paired in
+// one 64-bit word (FP32 for bricks that need it, one plane for main rows
+// and one for mirror rows); the tiles are then added to the projection with
+// one global atomic per non-zero pixel. Direct variant: global atomics per
+// tap.
 
 __device__ __forceinline__ void splat(float* __restrict__ qs, int32_t nu, int32_t nv, int32_t a,
                                       float du, int32_t ra, int32_t rb, float fr, float val) {
@@ -72,9 +74,10 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
 
 // Accumulation for the tiled adjoint. LDS float atomics are serialised on
 // gfx950: about 3 clocks per active lane per CU, 194 per full wave, against
-// 5 for an integer add of any width or lane count (measured). A brick's
-// splats therefore accumulate as 32-bit fixed point with integer LDS
-// atomics (exact and independent of order within the workgroup), unless
+// about 5.6 for a 32-bit integer add of a full wave and 7.5 for a 64-bit one
+// (measured). A brick's splats therefore accumulate as 32-bit fixed point
+// with integer LDS atomics (exact and independent of order within the
+// workgroup), a tap's main and mirror sums in one 64-bit add, unless
 // the brick is one of the two kinds fixed point cannot serve:
 //  - it holds a NaN or an infinity, which integers cannot carry; or
 //  - it spans a wide dynamic range: more than 1 % of its non-zero voxels lie
@@ -97,9 +100,10 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
 // keeps every partial sum, rounding included, inside int32. S is a power of
 // two, so the scaling is exact and cannot overflow however small or large
 // the values. A pixel's quantisation error is at most half a unit,
-// 2^(e - 32) ~ K M 2^-31, per contribution: relative to the brick's largest
-// splat, not to the pixel's own sum, which is why wide-range bricks go to
-// FP32.
+// 2^(e - 32) ~ K M 2^-31, per contribution (one unit for splats above 2^23
+// units, whose FP32 value is coarser than that anyway): relative to the
+// brick's largest splat, not to the pixel's own sum, which is why
+// wide-range bricks go to FP32.
 constexpr int32_t kHistStride = kThreads;  // tile columns tu + 1 <= 256
 constexpr int64_t kFpSplitTarget = 4096;    // workgroups below which views are split
 constexpr int kFpWideRangeLog2 = 13;        // "small" voxels: below 2^-13 of the brick's max
@@ -116,13 +120,34 @@ __device__ __forceinline__ void splat_f32(float* p, int32_t tvp, float val, floa
   atomicAdd(p + tvp + 1, fb * du);
 }
 
+// Fixed point of x: floor(x + 0.5) in one conversion, exact below 2^23
+// units and within one unit above (where the FP32 product feeding it is
+// already coarser than a unit).
+__device__ __forceinline__ int32_t fixed_round(float x) {
+  int32_t r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// Adds the fixed-point pair (a, b) to the 64-bit word at p, a into the low
+// half and b into the high half: the addend is the 64-bit integer
+// b 2^32 + a (a sign-extended), so every partial sum is exactly
+// (sum b) 2^32 + (sum a), and both halves decode exactly while each sum
+// stays inside int32. One 64-bit LDS add serves the row and its mirror.
+__device__ __forceinline__ void add_pair(uint64_t* p, float a, float b) {
+  const int32_t lo = fixed_round(a), hi = fixed_round(b);
+  const uint64_t word = (static_cast<uint64_t>(static_cast<uint32_t>(hi + (lo >> 31))) << 32) |
+                        static_cast<uint32_t>(lo);
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(word));
+}
+
 template <bool MIRROR>
 __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRun run,
                                                             ViewBatch vb, TileShape ts,
                                                             const float* __restrict__ vol,
                                                             float* __restrict__ q,
                                                             int64_t vstride, float scale) {
-  extern __shared__ int atile[];
+  extern __shared__ __attribute__((aligned(16))) int atile[];
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
   __shared__ uint32_t hist[kMaxStageViews * kHistStride];
   __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
@@ -184,11 +209,10 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
     // Main rows in planes [0, vc) and mirror rows in planes [vc, 2 vc), one
     // 32-bit word per pixel: all LDS banks serve the adds (interleaved
     // (main, mirror) pairs reached only half of them and conflicted 10-way).
+    // (The fixed-point path of mirrored runs uses the same bytes as 64-bit
+    // (main, mirror) words instead.)
     int* const mtile = atile + ts.vc * slot;
-    for (int32_t e = tid; e < nvc * slot; e += kThreads) {
-      atile[e] = 0;
-      if (MIRROR) mtile[e] = 0;
-    }
+    for (int32_t e = tid; e < (MIRROR ? 2 * ts.vc : nvc) * slot; e += kThreads) atile[e] = 0;
     if (!fp32_path) {
       for (int32_t e = tid; e < nvc * kHistStride; e += kThreads) hist[e] = 0u;
       if (tid < nvc) kcount[tid] = mbits[tid] = 0u;
@@ -225,11 +249,28 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
           int e;
           frexpf(km, &e);
           const float ws = ldexpf(c.w, 31 - e);  // W S, S = 2^(31 - e)
+          const float du0 = 1.0f - c.du;
+          if constexpr (MIRROR) {
+            // (main, mirror) pairs of 32-bit sums in 64-bit words.
+            uint64_t* const base = reinterpret_cast<uint64_t*>(atile) + sl * slot + nu * tvp + c.nvb;
+            uint64_t* const base1 = base + tvp;  // pixel column u + 1
+#pragma unroll
+            for (int t = 0; t < kBrickZ; ++t) {
+              uint32_t dn;
+              float fr;
+              voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
+              const float val = ws * x[t], vm = ws * xm[t];
+              const float wa = val - val * fr, wb = val * fr;
+              const float ma = vm - vm * fr, mb = vm * fr;
+              add_pair(base + dn, wa * du0, ma * du0);
+              add_pair(base1 + dn, wa * c.du, ma * c.du);
+              add_pair(base + dn + 1, wb * du0, mb * du0);
+              add_pair(base1 + dn + 1, wb * c.du, mb * c.du);
+            }
+            continue;
+          }
           int* const base = atile + sl * slot + nu * tvp + c.nvb;
           int* const base1 = base + tvp;  // pixel column u + 1
-          int* const mbase = mtile + sl * slot + nu * tvp + c.nvb;
-          int* const mbase1 = mbase + tvp;
-          const float du0 = 1.0f - c.du;
 #pragma unroll
           for (int t = 0; t < kBrickZ; ++t) {
             uint32_t dn;
@@ -237,18 +278,11 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
             voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
             const float val = ws * x[t];
             const float wa = val - val * fr, wb = val * fr;
-            atomicAdd(base + dn, __float2int_rn(wa * du0));
-            atomicAdd(base1 + dn, __float2int_rn(wa * c.du));
-            atomicAdd(base + dn + 1, __float2int_rn(wb * du0));
-            atomicAdd(base1 + dn + 1, __float2int_rn(wb * c.du));
-            if (MIRROR) {
-              const float vm = ws * xm[t];
-              const float ma = vm - vm * fr, mb = vm * fr;
-              atomicAdd(mbase + dn, __float2int_rn(ma * du0));
-              atomicAdd(mbase1 + dn, __float2int_rn(ma * c.du));
-              atomicAdd(mbase + dn + 1, __float2int_rn(mb * du0));
-              atomicAdd(mbase1 + dn + 1, __float2int_rn(mb * c.du));
-            } else {
+            atomicAdd(base + dn, fixed_round(wa * du0));
+            atomicAdd(base1 + dn, fixed_round(wa * c.du));
+            atomicAdd(base + dn + 1, fixed_round(wb * du0));
+            atomicAdd(base1 + dn + 1, fixed_round(wb * c.du));
+            {
               // The brick's upper 16 slices, into the same plane.
               uint32_t dn2;
               float fr2;
@@ -256,10 +290,10 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
                             kBrickZ + static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn2, &fr2);
               const float v2 = ws * xm[t];
               const float a2 = v2 - v2 * fr2, b2 = v2 * fr2;
-              atomicAdd(base + dn2, __float2int_rn(a2 * du0));
-              atomicAdd(base1 + dn2, __float2int_rn(a2 * c.du));
-              atomicAdd(base + dn2 + 1, __float2int_rn(b2 * du0));
-              atomicAdd(base1 + dn2 + 1, __float2int_rn(b2 * c.du));
+              atomicAdd(base + dn2, fixed_round(a2 * du0));
+              atomicAdd(base1 + dn2, fixed_round(a2 * c.du));
+              atomicAdd(base + dn2 + 1, fixed_round(b2 * du0));
+              atomicAdd(base1 + dn2 + 1, fixed_round(b2 * c.du));
             }
           }
         } else {
@@ -302,12 +336,24 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
         float* qs = q + s * vstride + gu;
         for (int32_t r = sr; r < tv; r += rstep) {
           const int32_t at = sl * slot + sc * tvp + r;
-          const float ex = fp32_path ? __int_as_float(atile[at]) : static_cast<float>(atile[at]) * inv_s;
+          float ex, ey = 0.0f;
+          if (fp32_path) {
+            ex = __int_as_float(atile[at]);
+            if (MIRROR) ey = __int_as_float(mtile[at]);
+          } else if (MIRROR) {
+            // Word = (mirror sum) 2^32 + (main sum), both int32.
+            const uint64_t w = reinterpret_cast<const uint64_t*>(atile)[at];
+            const int32_t lo = static_cast<int32_t>(static_cast<uint32_t>(w));
+            const int32_t hi = static_cast<int32_t>((w - static_cast<uint64_t>(static_cast<int64_t>(lo))) >> 32);
+            ex = static_cast<float>(lo) * inv_s;
+            ey = static_cast<float>(hi) * inv_s;
+          } else {
+            ex = static_cast<float>(atile[at]) * inv_s;
+          }
           const int32_t gr = bvs[s].org_v + r;
           if (ex != 0.0f && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv))
             unsafeAtomicAdd(qs + static_cast<int64_t>(gr) * gc.nu, ex);
           if (MIRROR) {
-            const float ey = fp32_path ? __int_as_float(mtile[at]) : static_cast<float>(mtile[at]) * inv_s;
             const int32_t gm = gc.mirror_g - gr;
             if (ey != 0.0f && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv))
               unsafeAtomicAdd(qs + static_cast<int64_t>(gm) * gc.nu, ey);
