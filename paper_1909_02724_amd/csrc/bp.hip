@@ -30,6 +30,7 @@ namespace {
 constexpr uint32_t kBadCol = 0x40000000u;  // pushes a buffer offset out of range
 constexpr uint32_t kBadRow = 0x80000000u;
 constexpr int kBufferWord3 = 0x00020000;   // raw buffer descriptor, gfx9 family
+constexpr int kDppWaveShl1 = 0x130;        // DPP: lane i reads lane i + 1 of the wave
 
 // Raw buffer load at vector offset off plus scalar (wave-uniform) offset soff.
 template <typename T>
@@ -72,15 +73,8 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
                                               int accumulate, float4* tile, BrickView* bvs) {
 
   const int32_t tid = threadIdx.x;
-  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-  // contiguous range of bricks so neighbours share footprints in its L2.
-  const uint32_t nwg = gridDim.x;
-  uint32_t lin = blockIdx.x;
-  if ((nwg & 7u) == 0) lin = (lin & 7u) * (nwg >> 3) + (lin >> 3);
-  const int32_t bx = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nbx));
-  lin /= static_cast<uint32_t>(ts.nbx);
-  const int32_t by = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nby));
-  const int32_t seg = static_cast<int32_t>(lin / static_cast<uint32_t>(ts.nby));
+  int32_t bx, by, seg;
+  brick_index(ts, &bx, &by, &seg);
 
   const int32_t i_lo = bx * kBrickX, j_lo = by * kBrickY;
   const int32_t i_hi = min(i_lo + kBrickX - 1, gc.nx - 1);
@@ -125,36 +119,41 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   if constexpr (TILED) {
     const int32_t tu = ts.tu, tv = ts.tv, tvp = ts.tvp, rstep = ts.rstep, rows = ts.rows;
     const int32_t slot_entries = tu * tvp;
-    // Staging assignment: thread -> tile column sc and rows sr + m * rstep
-    // (lanes along u, so global reads are coalesced).
-    const int32_t sr = tid / tu, sc = tid - sr * tu;
-    const bool stager = sr < rstep;
+    // Staging assignment: a tile row takes a group of L = 256 / rstep lanes
+    // (32 or 64, never straddling a wave), lane sc of the group loading
+    // pixel column org_u + sc for sc <= tu; thread -> column sc and rows
+    // sr + m rstep. Each lane loads one value per row (and mirror row); the
+    // next column's value, which completes the difference q(u + 1) - q(u),
+    // comes from the neighbouring lane. Lanes along u: coalesced reads.
+    const int32_t lanes = kBrickThreads / rstep;
+    const int32_t sr = tid / lanes, sc = tid - sr * lanes;
+    const bool loader = sc <= tu, stager = sc < tu;
     const uint32_t es = sizeof(T);
     const uint32_t row_es = static_cast<uint32_t>(gc.nu) * es;
     const uint32_t nrec = static_cast<uint32_t>(gc.nu) * static_cast<uint32_t>(gc.nv) * es;
-    // Raw bits of (q(u), q(u+1)) for the row and (mirrored runs) its mirror.
+    // Raw bits of q(u) for the row and (mirrored runs) its mirror row.
     constexpr int NSLOT = MIRROR ? kPrefetchSlots : kPlainPrefetchSlots;
-    uint4 pre[NSLOT];
+    uint2 pre[NSLOT];
 
     // Per-lane parts of the staging offsets, fixed for the launch: column sc
     // and first row sr relative to the tile origin, main rows downwards in
-    // the buffer and mirror rows upwards. Lanes that stage nothing start
+    // the buffer and mirror rows upwards. Lanes that load nothing start
     // from kBadRow, which a view's base offset and the row steps (a few MB
     // at most) keep out of range, so their loads return zero without a
     // fetch and need no select.
     const uint32_t t_main =
-        stager ? static_cast<uint32_t>(sr) * row_es + static_cast<uint32_t>(sc) * es : kBadRow;
+        loader ? static_cast<uint32_t>(sr) * row_es + static_cast<uint32_t>(sc) * es : kBadRow;
     const uint32_t t_mir =
-        stager ? static_cast<uint32_t>(sc) * es - static_cast<uint32_t>(sr) * row_es : kBadRow;
+        loader ? static_cast<uint32_t>(sc) * es - static_cast<uint32_t>(sr) * row_es : kBadRow;
     const uint32_t step = static_cast<uint32_t>(rstep) * row_es;
 
-    // Issue the loads of views [s0, s0 + nvc) into pre[]: raw (q(u), q(u+1))
-    // for the row and for its mirror row. A thread loads rows sr + rr rstep
-    // for every pass rr, also those at or beyond tv (the store drops them),
-    // so the loads need no row test. Views whose tile lies on the detector
-    // skip the range checks: rows past the tile may leave the detector, but
-    // their offsets then fall out of the buffer's range (below zero they
-    // wrap), which reads zero.
+    // Issue the loads of views [s0, s0 + nvc) into pre[]: raw q(u) of the
+    // row and of its mirror row. A thread loads rows sr + rr rstep for every
+    // pass rr, also those at or beyond tv (the store drops them), so the
+    // loads need no row test. Views whose tile lies on the detector skip the
+    // range checks: rows past the tile may leave the detector, but their
+    // offsets then fall out of the buffer's range (below zero they wrap),
+    // which reads zero.
     auto load_stage = [&](int32_t s0, int32_t nvc) {
       // Uniform, but the compiler may keep it in a vector register and then
       // treat every branch on it as divergent.
@@ -182,42 +181,30 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
           // Only the offsets depend on the branch: the loads themselves are
           // issued in common code, unconditionally (uniform control flow),
           // so nothing waits for them until the tile is written.
-          uint32_t o0, o1, m0, m1;
+          uint32_t o0, m0;
           if (inside) {
-            // q(u + 1) at the next element: the tile's last column plus one
-            // is on the detector, so it never crosses a row end.
+            // Columns org_u .. org_u + tu are on the detector.
             const uint32_t rs = static_cast<uint32_t>(rr) * step;
             o0 = off + rs;
-            o1 = off + (rs + es);
             m0 = offm - rs;
-            m1 = offm + (es - rs);
           } else {
             const int32_t gu = org_u + sc;
-            const uint32_t c0 = static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
+            const uint32_t c0 = loader && static_cast<uint32_t>(gu) < static_cast<uint32_t>(gc.nu)
                                     ? static_cast<uint32_t>(gu) * es : kBadCol;
-            const uint32_t c1 = static_cast<uint32_t>(gu + 1) < static_cast<uint32_t>(gc.nu)
-                                    ? static_cast<uint32_t>(gu + 1) * es : kBadCol;
             // (The uniform part is summed first: hoisted out of the stage
             // loop, per-slot lane values would be kept in spilled registers.)
             const int32_t gr = __builtin_amdgcn_readfirstlane(org_v + rr * rstep) + sr;
             const int32_t gm = MIRROR ? gc.mirror_g - gr : -1;
-            const uint32_t ro = stager && static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
+            const uint32_t ro = static_cast<uint32_t>(gr) < static_cast<uint32_t>(gc.nv)
                                     ? static_cast<uint32_t>(gr) * row_es : kBadRow;
-            const uint32_t rm = stager && static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
+            const uint32_t rm = static_cast<uint32_t>(gm) < static_cast<uint32_t>(gc.nv)
                                     ? static_cast<uint32_t>(gm) * row_es : kBadRow;
             o0 = ro + c0;
-            o1 = ro + c1;
             m0 = rm + c0;
-            m1 = rm + c1;
           }
-          uint4 p;
+          uint2 p;
           p.x = buf_load_raw<T>(rsrc, o0, 0);
-          p.y = buf_load_raw<T>(rsrc, o1, 0);
-          if (MIRROR) {
-            p.z = buf_load_raw<T>(rsrc, m0, 0);
-            p.w = buf_load_raw<T>(rsrc, m1, 0);
-          }
-          if (!MIRROR) p.z = p.w = 0u;
+          p.y = MIRROR ? buf_load_raw<T>(rsrc, m0, 0) : 0u;
           pre[m] = p;
         }
         if (++rr == rows) {
@@ -228,20 +215,31 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     };
 
     // Tile entry (sc, sr + rr rstep) of each view. Only the last pass can
-    // reach rows at or beyond tv, whose loads are discarded here.
+    // reach rows at or beyond tv, whose loads are discarded here. q(u + 1)
+    // is the next lane's q(u) (a wave-wide shift: lane sc < tu of a group
+    // always has its neighbour sc + 1 <= tu in the same group).
     const uint32_t lds_lane = static_cast<uint32_t>(sc * tvp + sr);
     const bool last_ok = stager && sr + (rows - 1) * rstep < tv;
+    auto next_lane = [](float x) {
+      return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kDppWaveShl1, 0xF,
+                                                        0xF, false));
+    };
     auto store_stage = [&](int32_t nvc) {
       nvc = __builtin_amdgcn_readfirstlane(nvc);
       int32_t sl = 0, rr = 0;
 #pragma unroll
       for (int m = 0; m < NSLOT; ++m) {
         if (sl < nvc) {
+          // All lanes take part in the shifts.
+          const float a0 = raw_to_f32<T>(pre[m].x), a1 = next_lane(a0);
+          float b0 = 0.0f, b1 = 0.0f;
+          if constexpr (MIRROR) {
+            b0 = raw_to_f32<T>(pre[m].y);
+            b1 = next_lane(b0);
+          }
           if (rr == rows - 1 ? last_ok : stager) {
             const uint32_t at = lds_lane + static_cast<uint32_t>(sl * slot_entries + rr * rstep);
-            const float a0 = raw_to_f32<T>(pre[m].x), a1 = raw_to_f32<T>(pre[m].y);
             if constexpr (MIRROR) {
-              const float b0 = raw_to_f32<T>(pre[m].z), b1 = raw_to_f32<T>(pre[m].w);
               tile[at] = make_float4(a0, a1 - a0, b0, b1 - b0);
             } else {
               reinterpret_cast<float2*>(tile)[at] = make_float2(a0, a1 - a0);

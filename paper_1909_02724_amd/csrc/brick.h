@@ -162,15 +162,34 @@ struct BrickCoords {
   bool owner;
 };
 
-__device__ __forceinline__ BrickCoords brick_coords(const GeoConst& gc, const SliceRun& run,
-                                                    const TileShape& ts, int32_t bz = kBrickZ) {
+// Brick (bx, by, z-segment) of this workgroup. Workgroups are dealt
+// round-robin to the 8 XCDs, and each XCD takes a contiguous range of a
+// linear order that runs over z-segments outermost and, within a segment,
+// over bands of kBandRows brick rows, column by column. The workgroups an
+// XCD holds at once (32 CUs x 4) then form a compact patch of bricks, about
+// 16 x 8, whose detector footprints in all the views of a launch fit its L2
+// together (a row of bricks across the volume would not).
+constexpr uint32_t kBandRows = 8;
+__device__ __forceinline__ void brick_index(const TileShape& ts, int32_t* bx, int32_t* by,
+                                            int32_t* seg) {
   const uint32_t nwg = gridDim.x;
   uint32_t lin = blockIdx.x;
   if ((nwg & 7u) == 0) lin = (lin & 7u) * (nwg >> 3) + (lin >> 3);
-  const int32_t bx = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nbx));
-  lin /= static_cast<uint32_t>(ts.nbx);
-  const int32_t by = static_cast<int32_t>(lin % static_cast<uint32_t>(ts.nby));
-  const int32_t seg = static_cast<int32_t>(lin / static_cast<uint32_t>(ts.nby));
+  const uint32_t nbx = static_cast<uint32_t>(ts.nbx), nby = static_cast<uint32_t>(ts.nby);
+  const uint32_t plane = nbx * nby;
+  const uint32_t sg = lin / plane, r = lin - sg * plane;
+  const uint32_t band = r / (kBandRows * nbx);
+  const uint32_t rows = min(kBandRows, nby - band * kBandRows);
+  const uint32_t rb = r - band * kBandRows * nbx;
+  *bx = static_cast<int32_t>(rb / rows);
+  *by = static_cast<int32_t>(band * kBandRows + rb % rows);
+  *seg = static_cast<int32_t>(sg);
+}
+
+__device__ __forceinline__ BrickCoords brick_coords(const GeoConst& gc, const SliceRun& run,
+                                                    const TileShape& ts, int32_t bz = kBrickZ) {
+  int32_t bx, by, seg;
+  brick_index(ts, &bx, &by, &seg);
   BrickCoords bc;
   bc.i_lo = bx * kBrickX;
   bc.j_lo = by * kBrickY;

@@ -327,9 +327,9 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
     for (const fdk::SliceRun& r : sl.runs) {
       const fdk::TileShape ts =
           r.mirror ? fdk::tile_shape(g, gc, r, vb, fdk::kBrickZ, fdk::kTileEntryBytes,
-                                     fdk::kPrefetchSlots, direct, true)
+                                     fdk::kPrefetchSlots, direct, true, true)
                    : fdk::tile_shape(g, gc, r, vb, fdk::kPlainBrickZ, fdk::kPlainEntryBytes,
-                                     fdk::kPlainPrefetchSlots, direct);
+                                     fdk::kPlainPrefetchSlots, direct, true);
       if (int e = fdk::launch_backproject(gc, r, vb, ts, qb, q_dtype, vstride, vol, scale,
                                           (b > 0) || acc0, stream))
         return fail(FDK_ERR_HIP, "back-projection launch failed: HIP error %d", e);

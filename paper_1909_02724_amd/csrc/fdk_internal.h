@@ -54,6 +54,7 @@ constexpr int kBrickX = 16;
 constexpr int kBrickY = 16;
 constexpr int kBrickZ = 16;
 constexpr int kBrickThreads = kBrickX * kBrickY;
+constexpr int kWaveLanes = 64;
 // Occupancy decides the back-projector's speed more than staging depth
 // does (measured on MI355X): four 256-thread workgroups per CU, hence at
 // most 36 KB of tiles and 128 VGPRs, with three views per stage, run 11 %
@@ -77,11 +78,13 @@ struct TileShape {
 // exceeds the LDS or prefetch budget, or the caller asks for the direct
 // variant (FDK_DIRECT).
 // bz: slices per brick; entry_bytes: LDS bytes per tile entry; slots: tile
-// entries a thread prefetches per stage; read_pitch: pad the column pitch for
-// the mirrored back-projector's conflict-free entry reads.
+// entries a thread prefetches per stage; bp_staging: the back-projector's
+// staging (lane groups per tile row) rather than the adjoint's; read_pitch:
+// pad the column pitch for the mirrored back-projector's conflict-free
+// entry reads.
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots,
-                     bool direct, bool read_pitch = false);
+                     bool direct, bool bp_staging = false, bool read_pitch = false);
 // Plain (unmirrored) back-projection runs: 32 slices per brick, the tile
 // holding (q, dq/du) of the main rows only; a prefetch slot holds one row's
 // pair instead of two, so twice as many fit the same registers.

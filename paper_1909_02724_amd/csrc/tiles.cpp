@@ -18,7 +18,7 @@ namespace fdk {
 // spread dz the rows span at most kv ((bz - 1) / zmin + |k - cz| dz / zmin^2).
 TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& run,
                      const ViewBatch& vb, int32_t bz, int32_t entry_bytes, int32_t slots,
-                     bool direct, bool read_pitch) {
+                     bool direct, bool bp_staging, bool read_pitch) {
   TileShape ts{};
   ts.rot_a = 1;
   ts.rot_b = 4;
@@ -52,8 +52,16 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
     // only if their columns are 7 or more apart.
     while (ts.tvp % 16 != 7 && ts.tvp % 16 != 9) ts.tvp += 2;
   }
-  if (ts.tu + 1 > kBrickThreads) return ts;  // staging and the adjoint's flush: a thread per column
-  ts.rstep = kBrickThreads / ts.tu;
+  if (bp_staging) {
+    // The back-projector stages a tile row with a group of 32 or 64 lanes
+    // (one wave at most): a lane per column and one more.
+    if (ts.tu + 1 > kWaveLanes) return ts;
+    ts.rstep = kBrickThreads / (ts.tu + 1 <= kWaveLanes / 2 ? kWaveLanes / 2 : kWaveLanes);
+  } else {
+    // The adjoint's flush: a thread per column.
+    if (ts.tu + 1 > kBrickThreads) return ts;
+    ts.rstep = kBrickThreads / ts.tu;
+  }
   ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
   const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * entry_bytes;
   int64_t vc = std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);

@@ -44,9 +44,10 @@ void check_run(const fdk_geometry& g, const fdk::GeoConst& gc, const fdk::SliceR
   using namespace fdk;
   const bool mirror = run.mirror != 0;
   const int32_t bz = mirror ? kBrickZ : kPlainBrickZ;
-  const TileShape ts = mirror ? tile_shape(&g, gc, run, vb, bz, kTileEntryBytes, kPrefetchSlots, false, true)
+  const TileShape ts = mirror ? tile_shape(&g, gc, run, vb, bz, kTileEntryBytes, kPrefetchSlots, false,
+                                           true, true)
                               : tile_shape(&g, gc, run, vb, bz, kPlainEntryBytes,
-                                           kPlainPrefetchSlots, false);
+                                           kPlainPrefetchSlots, false, true);
   ++st->geometries;
   if (ts.vc <= 0) {
     ++st->direct;
