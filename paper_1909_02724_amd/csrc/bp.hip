@@ -377,10 +377,10 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   }
 }
 
-// The mirrored tiled variant runs four 256-thread workgroups per CU (four
-// waves per SIMD): its LDS tiles fit 36 KB and it is held to 128 VGPRs.
+// The mirrored tiled variant runs five 256-thread workgroups per CU (five
+// waves per SIMD): its LDS tiles fit 30 KB and it is held to 102 VGPRs.
 template <typename T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 5)))
 void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
                             const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
                             float scale, int accumulate) {
@@ -389,9 +389,9 @@ void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape t
   bp_brick_body<T, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
 }
 
-// The plain tiled variant is held to the same four waves per SIMD.
+// The plain tiled variant is held to the same five waves per SIMD.
 template <typename T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void bp_tiled_plain_kernel(GeoConst gc, SliceRun run,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 5))) void bp_tiled_plain_kernel(GeoConst gc, SliceRun run,
                                                                   ViewBatch vb, TileShape ts,
                                                                   const T* __restrict__ q,
                                                                   int64_t vstride,

@@ -56,12 +56,16 @@ constexpr int kBrickZ = 16;
 constexpr int kBrickThreads = kBrickX * kBrickY;
 constexpr int kWaveLanes = 64;
 // Occupancy decides the back-projector's speed more than staging depth
-// does (measured on MI355X): four 256-thread workgroups per CU, hence at
-// most 36 KB of tiles and 128 VGPRs, with three views per stage, run 11 %
-// (FP32) to 47 % (FP16) faster than three workgroups with four views.
+// does (measured on MI355X): five 256-thread workgroups per CU, hence at
+// most 30 KB of tiles and 102 VGPRs, with two views per stage, run 5 %
+// faster than four with three views (and four with three 11 % (FP32) to
+// 47 % (FP16) faster than three with four). The adjoint stages up to three
+// views in 36 KB.
 constexpr int kMaxStageViews = 3;
-constexpr int kPrefetchSlots = 9;       // tile entries a thread prefetches per stage
-constexpr int kTileLdsBytes = 36864;    // LDS budget for the tiles of one stage
+constexpr int kBpStageViews = 2;
+constexpr int kPrefetchSlots = 6;       // tile entries a thread prefetches per stage
+constexpr int kTileLdsBytes = 36864;    // LDS budget for the adjoint's tiles of one stage
+constexpr int kBpTileLdsBytes = 30720;  // and for the back-projector's
 constexpr int kTileEntryBytes = 16;     // (q, dq/du) of a row and of its mirror row
 
 struct TileShape {

@@ -64,7 +64,8 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   }
   ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
   const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * entry_bytes;
-  int64_t vc = std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);
+  int64_t vc = bp_staging ? std::min<int64_t>(kBpStageViews, kBpTileLdsBytes / per_view)
+                          : std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);
   vc = std::min<int64_t>(vc, slots / ts.rows);
   ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
   return ts;
