@@ -47,26 +47,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "back-projection GUPS at 2048³/2048 views; FP16-store vs FP32; adjoint GUPS"
 
-# Chip constants (MI355X, gfx950): 256 CUs at 2.4 GHz; a SIMD retires one
-# 64-lane FP32 VALU instruction per 4 clocks, 4 SIMDs per CU -> 64 lane-ops/clk/CU.
-N_CU, CLOCK_HZ, VALU_LANES_PER_CLK = 256, 2.4e9, 64
-# LDS read bandwidth measured with a ds_read_b128 microbenchmark on MI355X: 93.2 TB/s,
-# 151.7 B/clk/CU at 2.4 GHz (above the 128 B/clk of the previous generation).
-LDS_BYTES_PER_CLK = 151.7
+# Chip constants (MI355X, gfx950), measured with one-kernel microbenchmarks:
+# 256 CUs at 2.4 GHz; a SIMD retires a 64-lane FP32 add, multiply or FMA (and
+# moves, bitwise ops, 32-bit integer adds) every 2 clocks, 4 SIMDs per CU ->
+# 128 lane-ops/clk/CU, the 157.3 TFLOP/s FP32 vector peak; conversions,
+# fractions, shifts and 3-operand integer ops take 4 clocks (half rate).
+# Scheme op counts below are in full-rate equivalents (a half-rate op
+# counts 2).
+N_CU, CLOCK_HZ, VALU_LANES_PER_CLK = 256, 2.4e9, 128
+# LDS: a conflict-free 64-lane ds_read_b128 every 4.6 clocks per CU
+# (222.6 B/clk/CU at 2.4 GHz); a 64-lane 64-bit integer LDS add every 6.4
+# clocks (79.6 B/clk/CU of read-modify-write).
+LDS_BYTES_PER_CLK = 222.6
+LDS_ATOMIC64_BYTES_PER_CLK = 79.6
 HBM_PEAK = 8.0e12
 # VALU work per voxel-view update of the mirrored, difference-staged scheme:
-# per voxel pair v, truncation, fraction and tap address (4, shared); per
-# voxel two u-interpolations (1 FMA each on the staged difference), one
-# v-interpolation (2) and the weighted accumulate (1): (4 + 2 * 5) / 2 = 7.
-VALU_OPS_PER_UPDATE = 7.0
+# per voxel pair v (1 FMA), truncation, fraction and tap address (3 half
+# rate, shared); per voxel two u-interpolations (1 FMA each on the staged
+# difference), one v-interpolation (2) and the weighted accumulate (1):
+# (1 + 2 * 3 + 2 * 5) / 2 = 8.5 full-rate equivalents.
+VALU_OPS_PER_UPDATE = 8.5
 LDS_BYTES_PER_UPDATE = 16.0  # 4 FP32 taps (value and u-difference of two rows)
-# The adjoint's scheme (32-bit fixed-point tile): per voxel W S x (1), the row
-# split (2), the four tap weights (4) and their conversions (4); per voxel
-# pair v, truncation and fraction (3, shared); the adds themselves are LDS
-# atomics: 11 + 1.5 = 12.5 VALU ops and four 4-byte LDS read-modify-writes
-# per update.
-ADJ_VALU_OPS_PER_UPDATE = 12.5
-ADJ_LDS_BYTES_PER_UPDATE = 32.0
+# The adjoint's scheme (fixed-point tile, a row's and its mirror row's sums
+# in one 64-bit word), in full-rate equivalents: per voxel W S x (1), the
+# row split (2), four tap weights (4) and four round-to-fixed conversions
+# (half rate: 8) -> 15; per voxel pair v (1), truncation, fraction and
+# address (half rate: 6) -> 7, and for each of the four 64-bit adds the sign
+# carry of the low half (a shift, half rate, and an add: 3) -> 12; per
+# update (2 * 15 + 7 + 12) / 2 = 24.5, and two 8-byte LDS read-modify-writes
+# (16 bytes).
+ADJ_VALU_OPS_PER_UPDATE = 24.5
+ADJ_LDS_BYTES_PER_UPDATE = 16.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "bp_tiled_mirror_kernel_bp2048_traffic.json")
 # Slab workload: views are filtered in 16-view chunks; two contiguous chunks
 # make one back-projection launch (the volume is read and written per launch).
@@ -427,7 +438,8 @@ def oracle_configs(oracle, threads):
 
 
 def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel, traffic,
-                valu_insts=None, valu_ops=VALU_OPS_PER_UPDATE, lds_bytes=LDS_BYTES_PER_UPDATE):
+                valu_insts=None, valu_ops=VALU_OPS_PER_UPDATE, lds_bytes=LDS_BYTES_PER_UPDATE,
+                lds_rate=LDS_BYTES_PER_CLK):
     """The kernel against its roofs: VALU issue at the scheme's minimal op
     count per update, LDS bandwidth at its bytes per update (the measured
     ds_read peak), HBM at the algorithmic bytes (the volume read and written
@@ -439,7 +451,7 @@ def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel
     achieved = gups(updates_per_launch, per_launch_s)
     valu_rate = N_CU * VALU_LANES_PER_CLK * CLOCK_HZ  # lane-ops per second
     valu_roof = valu_rate / valu_ops / 2 ** 30
-    lds_roof = N_CU * LDS_BYTES_PER_CLK * CLOCK_HZ / lds_bytes / 2 ** 30
+    lds_roof = N_CU * lds_rate * CLOCK_HZ / lds_bytes / 2 ** 30
     peak = min(valu_roof, lds_roof)
     nz = updates / (float(g.nx) * g.ny * views_per_launch * launches)
     alg_bytes = updates_per_launch * (8.0 / views_per_launch +
@@ -463,11 +475,13 @@ def roofline_of(ms_step, launches, updates, g, views_per_launch, q_bytes, kernel
         "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_bytes, 3),
     }
     if valu_insts is not None:
-        # Measured lane-ops per update (rocprofv3 SQ_INSTS_VALU x 64 lanes) and
-        # the VALU issue rate they imply at the achieved speed.
+        # Measured VALU instructions per update at lane level (rocprofv3
+        # SQ_INSTS_VALU x 64 lanes, full- and half-rate ops together) and
+        # the issue time they would take at the full rate: a lower bound on
+        # the VALU busy fraction at the achieved speed.
         ops = valu_insts * 64.0 / updates_per_launch
         out["valu_lane_ops_per_update_measured"] = round(ops, 3)
-        out["valu_issue_frac_measured"] = round(achieved * 2 ** 30 * ops / valu_rate, 4)
+        out["valu_busy_frac_lower_bound"] = round(achieved * 2 ** 30 * ops / valu_rate, 4)
     return out
 
 
@@ -656,7 +670,8 @@ def main():
             k: v for k, v in roofline_of(msa, math.ceil(nv_adj / 32), ua, g, 32, 4.0,
                                          "fp_tiled_kernel<true>", None,
                                          valu_ops=ADJ_VALU_OPS_PER_UPDATE,
-                                         lds_bytes=ADJ_LDS_BYTES_PER_UPDATE).items()
+                                         lds_bytes=ADJ_LDS_BYTES_PER_UPDATE,
+                                         lds_rate=LDS_ATOMIC64_BYTES_PER_CLK).items()
             if not (k.startswith("hbm") or k.startswith("traffic"))}
         log(f"adjoint: {result_extra['adjoint_gups']} GUPS (median of {reps}) over {nv_adj} "
             f"views spread over the circle (ms {['%.1f' % m for m in msl]})")
