@@ -79,6 +79,15 @@ typedef enum { FDK_SLAB_CONTIGUOUS = 0, FDK_SLAB_MIRROR_PAIR = 1 } fdk_slab_kind
 #define FDK_DIRECT 4u
 /* flags of fdk_sirt_iteration: clamp the updated volume at zero. */
 #define FDK_NONNEG 2u
+/* flags of fdk_forward_project: sum every finite brick in 32-bit fixed
+ * point, also bricks with a wide range of magnitudes, which by default sum
+ * in 64-bit fixed point or FP32 (see fdk_forward_project). Each pixel's
+ * error is then at most half a unit of about 2^-31 K M per contribution
+ * (K M bounds what one pixel can receive from the brick): relative to the
+ * brick's largest contributions rather than each pixel's own. Wide-range
+ * volumes run up to twice as fast. The iterative entry points
+ * (fdk_sirt_iteration, fdk_mlem_iteration) project this way. */
+#define FDK_FIXED_SUMS 8u
 
 /* Circular-orbit cone-beam geometry (Table 1; projection matrix Eq. 2).
  * The volume centre (voxel ((Nx-1)/2, (Ny-1)/2, (Nz-1)/2)) is on the
@@ -167,7 +176,13 @@ FDK_API fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t
  * coordinates and weights the back-projector uses. vol: device FP32 slab.
  * q: device FP32 (nviews, Nv, Nu), overwritten unless FDK_ACCUMULATE.
  * Within a workgroup the splats are summed in 32-bit fixed point, scaled per
- * brick and view so that no partial sum can overflow; the workgroups' sums
+ * brick and view so that no partial sum can overflow. A brick with a wide
+ * range of magnitudes (more than 1 % of its non-zero voxels below 2^-13 of
+ * its largest) sums in 64-bit fixed point instead (half a unit of about
+ * 2^-63 K M per contribution: a voxel 2^-40 of the largest reaches a pixel
+ * through a full-weight tap at about FP32 precision of its own size), and a
+ * brick holding NaN or infinity, or spanning more than 2^40, sums in FP32
+ * (unless FDK_FIXED_SUMS, which keeps every finite brick in 32 bits). The workgroups' sums
  * meet in FP32 atomics, so the last bits vary from run to run.
  * Errors: as fdk_backproject. */
 FDK_API fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nviews,

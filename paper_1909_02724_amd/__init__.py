@@ -33,6 +33,7 @@ FDK_OK, FDK_ERR_INVALID_ARG, FDK_ERR_UNSUPPORTED, FDK_ERR_HIP, FDK_ERR_OOM = ran
 FDK_ACCUMULATE = 1
 FDK_NONNEG = 2
 FDK_DIRECT = 4
+FDK_FIXED_SUMS = 8
 _DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
 _FILTERS = {"ramlak": 0, "ram-lak": 0, "shepp-logan": 1, "shepplogan": 1}
 _SLABS = {"contiguous": 0, "mirror_pair": 1}
@@ -202,10 +203,12 @@ def backproject(q: torch.Tensor, geom, angles, *, view0: int = 0, out: torch.Ten
 def forward_project(vol: torch.Tensor, geom, angles, *, view0: int = 0,
                     nviews: int | None = None, out: torch.Tensor | None = None, z0: int = 0,
                     slab: str = "contiguous", scale: float = 1.0,
-                    accumulate: bool = False, direct: bool = False) -> torch.Tensor:
+                    accumulate: bool = False, direct: bool = False,
+                    fixed_sums: bool = False) -> torch.Tensor:
     """Matched forward projection (exact adjoint of backproject) of a
     float32 slab into (nviews, Nv, Nu) float32 projections. direct=True runs
-    the direct variant instead of the LDS-tiled one."""
+    the direct variant instead of the LDS-tiled one; fixed_sums=True sums
+    wide-range bricks in 32-bit fixed point too (FDK_FIXED_SUMS)."""
     _dev(vol, "vol")
     if vol.dtype != torch.float32 or vol.dim() != 3 or vol.shape[1:] != (geom.ny, geom.nx):
         raise ValueError(f"vol must be float32 (nz_local, {geom.ny}, {geom.nx})")
@@ -220,7 +223,8 @@ def forward_project(vol: torch.Tensor, geom, angles, *, view0: int = 0,
     cg, _keep = _cgeom(geom, angles)
     _check(lib().fdk_forward_project(C.byref(cg), view0, nviews, C.c_void_p(vol.data_ptr()), z0,
                                      nzl, sk, C.c_void_p(out.data_ptr()), float(scale),
-                                     _flags(accumulate, direct), _stream(vol)))
+                                     _flags(accumulate, direct) | (FDK_FIXED_SUMS if fixed_sums else 0),
+                                     _stream(vol)))
     return out
 
 

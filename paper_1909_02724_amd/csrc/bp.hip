@@ -65,7 +65,7 @@ __device__ __forceinline__ float raw_to_f32<bf16_t>(uint32_t bits) {
   return __uint_as_float(bits << 16);
 }
 
-template <typename T, bool MIRROR, bool TILED>
+template <typename T, bool MIRROR, bool TILED, bool WIDE = false>
 __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun& run,
                                               const ViewBatch& vb, const TileShape& ts,
                                               const T* __restrict__ q, int64_t vstride,
@@ -132,7 +132,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     const uint32_t row_es = static_cast<uint32_t>(gc.nu) * es;
     const uint32_t nrec = static_cast<uint32_t>(gc.nu) * static_cast<uint32_t>(gc.nv) * es;
     // Raw bits of q(u) for the row and (mirrored runs) its mirror row.
-    constexpr int NSLOT = MIRROR ? kPrefetchSlots : kPlainPrefetchSlots;
+    constexpr int NSLOT = (MIRROR ? 1 : 2) * (WIDE ? kWidePrefetchSlots : kPrefetchSlots);
     uint2 pre[NSLOT];
 
     // Per-lane parts of the staging offsets, fixed for the launch: column sc
@@ -377,8 +377,10 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   }
 }
 
-// The mirrored tiled variant runs five 256-thread workgroups per CU (five
-// waves per SIMD): its LDS tiles fit 30 KB and it is held to 102 VGPRs.
+// The tiled variants run five 256-thread workgroups per CU (five waves per
+// SIMD): tiles within 30 KB, 102 VGPRs. Tiles that need more staging passes
+// per view than their prefetch slots allow run the WIDE instances: four
+// workgroups per CU, 36 KB, 128 VGPRs and kWidePrefetchSlots slots.
 template <typename T>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 5)))
 void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
@@ -389,17 +391,36 @@ void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape t
   bp_brick_body<T, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
 }
 
-// The plain tiled variant is held to the same five waves per SIMD.
 template <typename T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 5))) void bp_tiled_plain_kernel(GeoConst gc, SliceRun run,
-                                                                  ViewBatch vb, TileShape ts,
-                                                                  const T* __restrict__ q,
-                                                                  int64_t vstride,
-                                                                  float* __restrict__ vol,
-                                                                  float scale, int accumulate) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void bp_tiled_mirror_wide_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                                 const T* __restrict__ q, int64_t vstride,
+                                 float* __restrict__ vol, float scale, int accumulate) {
+  extern __shared__ float4 tile[];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  bp_brick_body<T, true, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile,
+                                     bvs);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 5)))
+void bp_tiled_plain_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                           const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
+                           float scale, int accumulate) {
   extern __shared__ float4 tile[];
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
   bp_brick_body<T, false, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void bp_tiled_plain_wide_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                                const T* __restrict__ q, int64_t vstride,
+                                float* __restrict__ vol, float scale, int accumulate) {
+  extern __shared__ float4 tile[];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  bp_brick_body<T, false, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile,
+                                      bvs);
 }
 
 template <typename T, bool MIRROR>
@@ -424,8 +445,14 @@ int launch_bp_t(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb, co
   if (ts.vc > 0) {
     const size_t lds = static_cast<size_t>(ts.vc) * ts.tu * ts.tvp *
                        (run.mirror ? kTileEntryBytes : kPlainEntryBytes);
-    if (run.mirror)
+    if (run.mirror && ts.wide)
+      hipLaunchKernelGGL((bp_tiled_mirror_wide_kernel<T>), grid, block, lds, st, gc, run, vb, ts,
+                         qt, vstride, vol, scale, accumulate);
+    else if (run.mirror)
       hipLaunchKernelGGL((bp_tiled_mirror_kernel<T>), grid, block, lds, st, gc, run, vb, ts,
+                         qt, vstride, vol, scale, accumulate);
+    else if (ts.wide)
+      hipLaunchKernelGGL((bp_tiled_plain_wide_kernel<T>), grid, block, lds, st, gc, run, vb, ts,
                          qt, vstride, vol, scale, accumulate);
     else
       hipLaunchKernelGGL((bp_tiled_plain_kernel<T>), grid, block, lds, st, gc, run, vb, ts,

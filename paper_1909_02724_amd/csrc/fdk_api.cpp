@@ -348,13 +348,14 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
   if (!vol) return fail(FDK_ERR_INVALID_ARG, "volume pointer is NULL");
   if (nviews > 0 && !q) return fail(FDK_ERR_INVALID_ARG, "projection pointer is NULL");
   if (!std::isfinite(scale)) return fail(FDK_ERR_INVALID_ARG, "scale is not finite");
-  if (flags & ~(FDK_ACCUMULATE | FDK_DIRECT))
+  if (flags & ~(FDK_ACCUMULATE | FDK_DIRECT | FDK_FIXED_SUMS))
     return fail(FDK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
   const fdk::GeoConst gc = make_geo(g);
   Slab sl;
   if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   if (nviews == 0) return ok();
   const bool direct = flags & FDK_DIRECT;
+  const bool fixed_sums = flags & FDK_FIXED_SUMS;
   const int64_t vstride = (int64_t)g->nu * g->nv;
   if (!(flags & FDK_ACCUMULATE)) {
     if (int e = fdk::launch_fill_zero(q, vstride * nviews, stream))
@@ -374,7 +375,7 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
                                      std::numeric_limits<int32_t>::max(), direct);
       choose_rotation(gc, r, vb, r.mirror ? fdk::kBrickZ : fdk::kPlainBrickZ, &ts);
       if (int e = fdk::launch_forward_project(gc, r, vb, ts, vol, q + (size_t)b * vstride,
-                                              vstride, scale, stream))
+                                              vstride, scale, fixed_sums, stream))
         return fail(FDK_ERR_HIP, "forward-projection launch failed: HIP error %d", e);
     }
   }
@@ -502,7 +503,8 @@ fdk_status fdk_sirt_iteration(const fdk_geometry* g, int32_t view0, int32_t nvie
   Slab sl;
   if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   const int64_t nproj = (int64_t)nviews * g->nu * g->nv, nvox = slab_voxels(g, nz_local);
-  if ((st = fdk_forward_project(g, view0, nviews, x, z0, nz_local, slab, proj_tmp, 1.0f, 0, stream)))
+  if ((st = fdk_forward_project(g, view0, nviews, x, z0, nz_local, slab, proj_tmp, 1.0f,
+                                FDK_FIXED_SUMS, stream)))
     return st;
   int e = fdk::launch_sirt_residual(p, row_inv, proj_tmp, nproj, stream);
   if (e) return fail(FDK_ERR_HIP, "residual failed: HIP error %d", e);
@@ -560,7 +562,8 @@ fdk_status fdk_mlem_iteration(const fdk_geometry* g, int32_t view0, int32_t nvie
   Slab sl;
   if ((st = make_slab(g, gc, z0, nz_local, raw(slab), &sl))) return st;
   const int64_t nproj = (int64_t)nviews * g->nu * g->nv, nvox = slab_voxels(g, nz_local);
-  if ((st = fdk_forward_project(g, view0, nviews, x, z0, nz_local, slab, proj_tmp, 1.0f, 0, stream)))
+  if ((st = fdk_forward_project(g, view0, nviews, x, z0, nz_local, slab, proj_tmp, 1.0f,
+                                FDK_FIXED_SUMS, stream)))
     return st;
   // The ratio's max-reduction word lives in vol_tmp, which the
   // back-projection overwrites only afterwards (stream order).

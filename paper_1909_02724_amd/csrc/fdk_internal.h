@@ -64,14 +64,18 @@ constexpr int kWaveLanes = 64;
 constexpr int kMaxStageViews = 3;
 constexpr int kBpStageViews = 2;
 constexpr int kPrefetchSlots = 6;       // tile entries a thread prefetches per stage
-constexpr int kTileLdsBytes = 36864;    // LDS budget for the adjoint's tiles of one stage
-constexpr int kBpTileLdsBytes = 30720;  // and for the back-projector's
+// Tiles too tall for the five-wave back-projector's slots (more than three
+// staging passes per view) go to a four-wave instance with more slots.
+constexpr int kWidePrefetchSlots = 12;
+constexpr int kTileLdsBytes = 36864;    // LDS budget for the adjoint's and the four-wave tiles
+constexpr int kBpTileLdsBytes = 30720;  // and for the five-wave back-projector's
 constexpr int kTileEntryBytes = 16;     // (q, dq/du) of a row and of its mirror row
 
 struct TileShape {
   int32_t tu, tv, tvp;   // tile columns, rows, and the (odd) column pitch in entries
   int32_t vc;            // views staged at once; 0 selects the direct variant
   int32_t rstep, rows;   // staging: rows advanced per pass, passes per view
+  int32_t wide;          // back-projector: the four-wave instance with kWidePrefetchSlots
   int32_t nbx, nby, nseg;  // bricks along x, y and z-segments of the run
   // Adjoint: lane (tx, ty) visits its slots from (rot_a tx + rot_b (ty mod 4))
   // mod 16 on, which spreads the lanes' LDS adds over the banks.
@@ -103,6 +107,6 @@ int launch_backproject(const GeoConst& gc, const SliceRun& run, const ViewBatch&
                        void* stream);
 int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
                            const TileShape& ts, const float* vol, float* q, int64_t view_stride,
-                           float scale, void* stream);
+                           float scale, bool fixed_sums, void* stream);
 int launch_fill_zero(float* p, int64_t n, void* stream);
 }  // namespace fdk

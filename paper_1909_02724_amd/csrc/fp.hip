@@ -74,17 +74,26 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
 
 // Accumulation for the tiled adjoint. LDS float atomics are serialised on
 // gfx950: about 3 clocks per active lane per CU, 194 per full wave, against
-// about 5.6 for a 32-bit integer add of a full wave and 7.5 for a 64-bit one
+// about 4.6 for a 32-bit integer add of a full wave and 6.4 for a 64-bit one
 // (measured). A brick's splats therefore accumulate as 32-bit fixed point
 // with integer LDS atomics (exact and independent of order within the
-// workgroup), a tap's main and mirror sums in one 64-bit add, unless
-// the brick is one of the two kinds fixed point cannot serve:
-//  - it holds a NaN or an infinity, which integers cannot carry; or
-//  - it spans a wide dynamic range: more than 1 % of its non-zero voxels lie
-//    below 2^-13 of its largest magnitude.
-// Those bricks take FP32 atomics (float tile, same layout), so each pixel's
-// sum carries FP32 rounding relative to its own contributions and
-// non-finite values reach exactly the pixels they touch.
+// workgroup), a tap's main and mirror sums in one 64-bit add, unless the
+// brick spans a wide dynamic range: more than 1 % of its non-zero voxels
+// lie below 2^-13 of its largest magnitude. Such a brick accumulates in
+// 64-bit fixed point (the same scale rule with 2^63, one 64-bit add per
+// tap), half a unit (about 2^-63 K M) per contribution: a voxel 2^-40 of
+// the largest reaches a pixel through a full-weight tap at about 2^-24 K
+// relative precision, so this serves bricks whose non-zero magnitudes span
+// at most 2^40 (taps with weights near zero keep the absolute bound only).
+// Two kinds take FP32 atomics (float tile, planar layout) instead:
+//  - a brick with a NaN or an infinity, which integers cannot carry;
+//  - a wide-range brick spanning more than 2^40, or one whose launch stages
+//    a single view (its 64-bit tile would not fit).
+// The FP32 path is slow (a workgroup on it can take longer than the rest of
+// its launch), so it is kept for what fixed point cannot represent.
+// On the FP32 path each pixel's sum carries FP32 rounding relative to its
+// own contributions and non-finite values reach exactly the pixels they
+// touch.
 //
 // Fixed-point scale, per brick and view, from a bound on what one pixel can
 // receive:
@@ -103,16 +112,19 @@ __device__ __forceinline__ void load_voxels(const GeoConst& gc, const SliceRun& 
 // 2^(e - 32) ~ K M 2^-31, per contribution (one unit for splats above 2^23
 // units, whose FP32 value is coarser than that anyway): relative to the
 // brick's largest splat, not to the pixel's own sum, which is why
-// wide-range bricks go to FP32.
+// wide-range bricks take 64 bits or FP32.
 constexpr int32_t kHistStride = kThreads;  // tile columns tu + 1 <= 256
 constexpr int64_t kFpSplitTarget = 4096;    // workgroups below which views are split
 constexpr int kFpWideRangeLog2 = 13;        // "small" voxels: below 2^-13 of the brick's max
-constexpr int kFpWideRangePct = 1;          // FP32 path above 1 % small voxels
+constexpr int kFpWideRangePct = 1;          // wide-range path above 1 % small voxels
+constexpr int kFp64RangeLog2 = 40;          // 64-bit fixed point up to this magnitude range
 
 // FP32 splat (FP32 path): taps (u, n), (u + 1, n), (u, n + 1),
 // (u + 1, n + 1) of a tile with column pitch tvp.
 __device__ __forceinline__ void splat_f32(float* p, int32_t tvp, float val, float fr, float du) {
-  const float fb = val * fr, fa = val - fb;
+  // (1 - fr) first: val - val fr would carry the rounding of val fr, up to
+  // 2^-25 val, into a near-zero weight.
+  const float fb = val * fr, fa = val * (1.0f - fr);
   const float du0 = 1.0f - du;
   atomicAdd(p, fa * du0);
   atomicAdd(p + tvp, fa * du);
@@ -141,17 +153,24 @@ __device__ __forceinline__ void add_pair(uint64_t* p, float a, float b) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(word));
 }
 
+// Adds x, rounded to the nearest integer, to the 64-bit fixed-point sum at p.
+__device__ __forceinline__ void add_fixed64(uint64_t* p, float x) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p),
+            static_cast<unsigned long long>(__float2ll_rn(x)));
+}
+
 template <bool MIRROR>
 __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRun run,
                                                             ViewBatch vb, TileShape ts,
                                                             const float* __restrict__ vol,
                                                             float* __restrict__ q,
-                                                            int64_t vstride, float scale) {
+                                                            int64_t vstride, float scale,
+                                                            int fixed_sums) {
   extern __shared__ __attribute__((aligned(16))) int atile[];
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
   __shared__ uint32_t hist[kMaxStageViews * kHistStride];
   __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
-  __shared__ uint32_t amax_bits, n_nonzero, n_small, nonfinite;
+  __shared__ uint32_t amax_bits, amin_bits, n_nonzero, n_small, nonfinite;
   const int32_t tid = threadIdx.x;
   constexpr int BZ = MIRROR ? kBrickZ : kPlainBrickZ;  // slices per brick
   // blockIdx.y picks this workgroup's share of the launch's views: small
@@ -163,24 +182,31 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   const int32_t v_hi = min(vb.nviews, v_lo + per);
   if (v_lo >= v_hi) return;  // uniform, before any barrier
   const BrickCoords bc = brick_coords(gc, run, ts, BZ);
-  if (tid == 0) amax_bits = n_nonzero = n_small = nonfinite = 0u;
+  if (tid == 0) {
+    amax_bits = n_nonzero = n_small = nonfinite = 0u;
+    amin_bits = __float_as_uint(INFINITY);
+  }
   if (tid >= v_lo && tid < v_hi)
     bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
                            MIRROR);
   const uint32_t rot = slot_rotation(ts);
   float x[kBrickZ], xm[kBrickZ];
   load_voxels<MIRROR>(gc, run, bc, vol, scale, rot, x, xm);
-  // Brick statistics: largest magnitude, non-finite values (x - x is NaN
-  // exactly for those), then how many non-zero voxels are small against it.
-  float amax = 0.0f;
+  // Brick statistics: largest and smallest non-zero magnitudes, non-finite
+  // values (x - x is NaN exactly for those), then how many non-zero voxels
+  // are small against the largest.
+  float amax = 0.0f, amin = INFINITY;
   bool bad = false;
 #pragma unroll
   for (int t = 0; t < kBrickZ; ++t) {
     amax = fmaxf(amax, fmaxf(fabsf(x[t]), fabsf(xm[t])));
+    amin = fminf(amin, fminf(x[t] != 0.0f ? fabsf(x[t]) : INFINITY,
+                             xm[t] != 0.0f ? fabsf(xm[t]) : INFINITY));
     bad = bad || ((x[t] - x[t]) != 0.0f) || ((xm[t] - xm[t]) != 0.0f);
   }
   __syncthreads();
   atomicMax(&amax_bits, __float_as_uint(amax));  // non-negative floats order as integers
+  atomicMin(&amin_bits, __float_as_uint(amin));
   if (bad) nonfinite = 1u;
   __syncthreads();
   {
@@ -196,23 +222,35 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
   }
   __syncthreads();
   if (amax_bits == 0u && nonfinite == 0u) return;  // an all-zero brick adds nothing (uniform)
-  const bool fp32_path =
-      nonfinite != 0u || 100u * n_small > static_cast<uint32_t>(kFpWideRangePct) * n_nonzero;
+  // Accumulation of the brick (uniform): 32-bit fixed point; 64-bit fixed
+  // point for a wide-range brick whose non-zero magnitudes span at most
+  // 2^kFp64RangeLog2, with half the views per stage (its entries take twice
+  // the bytes); FP32 for a brick with non-finite values, a wider range, or
+  // when a stage holds a single view.
+  // (With fixed_sums every finite brick takes 32 bits.)
+  const bool wide_range =
+      !fixed_sums && 100u * n_small > static_cast<uint32_t>(kFpWideRangePct) * n_nonzero;
+  const bool fixed64 = nonfinite == 0u && wide_range && ts.vc >= 2 &&
+                       __uint_as_float(amax_bits) <=
+                           ldexpf(__uint_as_float(amin_bits), kFp64RangeLog2);
+  const bool fp32_path = nonfinite != 0u || (wide_range && !fixed64);
+  const int32_t vstep = fixed64 ? ts.vc / 2 : ts.vc;
 
   const float kvf = static_cast<float>(gc.kv);
   const int32_t tuf = ts.tu + 1, tv = ts.tv, tvp = ts.tvp;
   const int32_t slot = tuf * tvp;
   const int32_t rstep = kThreads / tuf;
   const int32_t sr = tid / tuf, sc = tid - sr * tuf;
-  for (int32_t s0 = v_lo; s0 < v_hi; s0 += ts.vc) {
-    const int32_t nvc = min(ts.vc, v_hi - s0);
+  for (int32_t s0 = v_lo; s0 < v_hi; s0 += vstep) {
+    const int32_t nvc = min(vstep, v_hi - s0);
     // Main rows in planes [0, vc) and mirror rows in planes [vc, 2 vc), one
     // 32-bit word per pixel: all LDS banks serve the adds (interleaved
     // (main, mirror) pairs reached only half of them and conflicted 10-way).
-    // (The fixed-point path of mirrored runs uses the same bytes as 64-bit
-    // (main, mirror) words instead.)
+    // (The 32-bit fixed-point path of mirrored runs uses the same bytes as
+    // 64-bit (main, mirror) words instead, the 64-bit one as 16-byte
+    // (main, mirror) entries, and that of plain runs as 64-bit words.)
     int* const mtile = atile + ts.vc * slot;
-    for (int32_t e = tid; e < (MIRROR ? 2 * ts.vc : nvc) * slot; e += kThreads) atile[e] = 0;
+    for (int32_t e = tid; e < (MIRROR ? 2 : 1) * ts.vc * slot; e += kThreads) atile[e] = 0;
     if (!fp32_path) {
       for (int32_t e = tid; e < nvc * kHistStride; e += kThreads) hist[e] = 0u;
       if (tid < nvc) kcount[tid] = mbits[tid] = 0u;
@@ -248,8 +286,60 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
           if (!(km > 0.0f)) continue;  // nothing reaches this view (uniform)
           int e;
           frexpf(km, &e);
-          const float ws = ldexpf(c.w, 31 - e);  // W S, S = 2^(31 - e)
           const float du0 = 1.0f - c.du;
+          if (fixed64) {
+            // S = 2^(63 - e), applied to W x (at most M) so that no
+            // intermediate overflows.
+            const int sh = 63 - e;
+            if constexpr (MIRROR) {
+              uint64_t* const base =
+                  reinterpret_cast<uint64_t*>(atile) + 2 * (sl * slot + nu * tvp + c.nvb);
+              uint64_t* const base1 = base + 2 * tvp;  // pixel column u + 1
+#pragma unroll
+              for (int t = 0; t < kBrickZ; ++t) {
+                uint32_t dn;
+                float fr;
+                voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
+                const float val = ldexpf(c.w * x[t], sh), vm = ldexpf(c.w * xm[t], sh);
+                const float wa = val * (1.0f - fr), wb = val * fr;
+                const float ma = vm * (1.0f - fr), mb = vm * fr;
+                uint64_t* const p = base + 2 * dn;
+                uint64_t* const p1 = base1 + 2 * dn;
+                add_fixed64(p, wa * du0);
+                add_fixed64(p + 1, ma * du0);
+                add_fixed64(p1, wa * c.du);
+                add_fixed64(p1 + 1, ma * c.du);
+                add_fixed64(p + 2, wb * du0);
+                add_fixed64(p + 3, mb * du0);
+                add_fixed64(p1 + 2, wb * c.du);
+                add_fixed64(p1 + 3, mb * c.du);
+              }
+            } else {
+              uint64_t* const base = reinterpret_cast<uint64_t*>(atile) + sl * slot + nu * tvp + c.nvb;
+              uint64_t* const base1 = base + tvp;
+#pragma unroll
+              for (int t = 0; t < kBrickZ; ++t) {
+                const int32_t tt = static_cast<int32_t>((t + rot) & (kBrickZ - 1));
+                uint32_t dn, dn2;
+                float fr, fr2;
+                voxel_row_off(c.fvb, c.dvk, tt, &dn, &fr);
+                voxel_row_off(c.fvb, c.dvk, kBrickZ + tt, &dn2, &fr2);
+                const float val = ldexpf(c.w * x[t], sh), v2 = ldexpf(c.w * xm[t], sh);
+                const float wa = val * (1.0f - fr), wb = val * fr;
+                const float a2 = v2 * (1.0f - fr2), b2 = v2 * fr2;
+                add_fixed64(base + dn, wa * du0);
+                add_fixed64(base1 + dn, wa * c.du);
+                add_fixed64(base + dn + 1, wb * du0);
+                add_fixed64(base1 + dn + 1, wb * c.du);
+                add_fixed64(base + dn2, a2 * du0);
+                add_fixed64(base1 + dn2, a2 * c.du);
+                add_fixed64(base + dn2 + 1, b2 * du0);
+                add_fixed64(base1 + dn2 + 1, b2 * c.du);
+              }
+            }
+            continue;
+          }
+          const float ws = ldexpf(c.w, 31 - e);  // W S, S = 2^(31 - e)
           if constexpr (MIRROR) {
             // (main, mirror) pairs of 32-bit sums in 64-bit words.
             uint64_t* const base = reinterpret_cast<uint64_t*>(atile) + sl * slot + nu * tvp + c.nvb;
@@ -260,8 +350,8 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
               float fr;
               voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
               const float val = ws * x[t], vm = ws * xm[t];
-              const float wa = val - val * fr, wb = val * fr;
-              const float ma = vm - vm * fr, mb = vm * fr;
+              const float wa = val * (1.0f - fr), wb = val * fr;
+              const float ma = vm * (1.0f - fr), mb = vm * fr;
               add_pair(base + dn, wa * du0, ma * du0);
               add_pair(base1 + dn, wa * c.du, ma * c.du);
               add_pair(base + dn + 1, wb * du0, mb * du0);
@@ -277,7 +367,7 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
             float fr;
             voxel_row_off(c.fvb, c.dvk, static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn, &fr);
             const float val = ws * x[t];
-            const float wa = val - val * fr, wb = val * fr;
+            const float wa = val * (1.0f - fr), wb = val * fr;
             atomicAdd(base + dn, fixed_round(wa * du0));
             atomicAdd(base1 + dn, fixed_round(wa * c.du));
             atomicAdd(base + dn + 1, fixed_round(wb * du0));
@@ -289,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
               voxel_row_off(c.fvb, c.dvk,
                             kBrickZ + static_cast<int32_t>((t + rot) & (kBrickZ - 1)), &dn2, &fr2);
               const float v2 = ws * xm[t];
-              const float a2 = v2 - v2 * fr2, b2 = v2 * fr2;
+              const float a2 = v2 * (1.0f - fr2), b2 = v2 * fr2;
               atomicAdd(base + dn2, fixed_round(a2 * du0));
               atomicAdd(base1 + dn2, fixed_round(a2 * c.du));
               atomicAdd(base + dn2 + 1, fixed_round(b2 * du0));
@@ -326,12 +416,15 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
         const int32_t s = s0 + sl;
         const int32_t gu = bvs[s].org_u + sc;
         if (static_cast<uint32_t>(gu) >= static_cast<uint32_t>(gc.nu)) continue;
-        // Value of one fixed-point unit, 2^(e - 31) (unused on the FP32 path).
+        // Value of one fixed-point unit: 2^(e - 31), or 2^(e - 63) for the
+        // 64-bit path (unused on the FP32 path).
         float inv_s = 0.0f;
+        double inv_s64 = 0.0;
         if (!fp32_path) {
           int e;
           frexpf(1.01f * static_cast<float>(kcount[sl]) * __uint_as_float(mbits[sl]), &e);
           inv_s = ldexpf(1.0f, e - 31);
+          inv_s64 = ldexp(1.0, e - 63);
         }
         float* qs = q + s * vstride + gu;
         for (int32_t r = sr; r < tv; r += rstep) {
@@ -340,6 +433,10 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
           if (fp32_path) {
             ex = __int_as_float(atile[at]);
             if (MIRROR) ey = __int_as_float(mtile[at]);
+          } else if (fixed64) {
+            const int64_t* const w = reinterpret_cast<const int64_t*>(atile);
+            ex = static_cast<float>(static_cast<double>(w[MIRROR ? 2 * at : at]) * inv_s64);
+            if (MIRROR) ey = static_cast<float>(static_cast<double>(w[2 * at + 1]) * inv_s64);
           } else if (MIRROR) {
             // Word = (mirror sum) 2^32 + (main sum), both int32.
             const uint64_t w = reinterpret_cast<const uint64_t*>(atile)[at];
@@ -421,7 +518,7 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t n) {
 
 int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBatch& vb,
                            const TileShape& ts, const float* vol, float* q, int64_t vstride,
-                           float scale, void* stream) {
+                           float scale, bool fixed_sums, void* stream) {
   const uint64_t nwg = static_cast<uint64_t>(ts.nbx) * ts.nby * ts.nseg;
   const dim3 block(kThreads);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -445,10 +542,10 @@ int launch_forward_project(const GeoConst& gc, const SliceRun& run, const ViewBa
     const size_t lds = static_cast<size_t>(tf.vc) * per_view;
     if (run.mirror)
       hipLaunchKernelGGL((fp_tiled_kernel<true>), grid, block, lds, st, gc, run, vb, tf, vol,
-                         q, vstride, scale);
+                         q, vstride, scale, static_cast<int>(fixed_sums));
     else
       hipLaunchKernelGGL((fp_tiled_kernel<false>), grid, block, lds, st, gc, run, vb, tf, vol,
-                         q, vstride, scale);
+                         q, vstride, scale, static_cast<int>(fixed_sums));
   } else {
     const dim3 grid(static_cast<uint32_t>(nwg));
     if (run.mirror)

@@ -64,10 +64,19 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   }
   ts.rows = (ts.tv + ts.rstep - 1) / ts.rstep;
   const int64_t per_view = static_cast<int64_t>(ts.tu) * ts.tvp * entry_bytes;
-  int64_t vc = bp_staging ? std::min<int64_t>(kBpStageViews, kBpTileLdsBytes / per_view)
-                          : std::min<int64_t>(kMaxStageViews, kTileLdsBytes / per_view);
-  vc = std::min<int64_t>(vc, slots / ts.rows);
-  ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
+  if (!bp_staging) {
+    const int64_t vc = std::min<int64_t>({kMaxStageViews, kTileLdsBytes / per_view, slots / ts.rows});
+    ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
+    return ts;
+  }
+  // Back-projector: the five-wave kernel (slots prefetch slots, 30 KB of
+  // tiles) when it stages all kBpStageViews views per stage, else the
+  // four-wave one (more slots and 36 KB) if that stages more.
+  const int64_t vc5 = std::min<int64_t>({kBpStageViews, kBpTileLdsBytes / per_view, slots / ts.rows});
+  const int64_t wide_slots = static_cast<int64_t>(slots) * kWidePrefetchSlots / kPrefetchSlots;
+  const int64_t vc4 = std::min<int64_t>({kBpStageViews, kTileLdsBytes / per_view, wide_slots / ts.rows});
+  ts.wide = vc5 < kBpStageViews && vc4 > vc5;
+  ts.vc = static_cast<int32_t>(std::max<int64_t>(ts.wide ? vc4 : vc5, 0));
   return ts;
 }
 

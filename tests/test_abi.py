@@ -100,6 +100,8 @@ def test_forward_and_filter_validation():
     assert L.fdk_forward_project(C.byref(cg), 0, 4, None, 0, 8, 0, FAKE, 1.0, 0, None) == 1
     assert "volume pointer" in L.fdk_last_error().decode()
     assert L.fdk_forward_project(C.byref(cg), 11, 4, FAKE, 0, 8, 0, FAKE, 1.0, 0, None) == 1
+    assert L.fdk_forward_project(C.byref(cg), 0, 4, FAKE, 0, 8, 0, FAKE, 1.0, 16, None) == 1
+    assert "flags" in L.fdk_last_error().decode()
     assert L.fdk_filter(C.byref(cg), 0, 4, FAKE, FAKE, 0, 9, None) == 2
     assert "filter kind" in L.fdk_last_error().decode()
     assert L.fdk_filter(C.byref(cg), 0, 4, FAKE, FAKE, 5, 0, None) == 2
