@@ -160,12 +160,10 @@ __device__ __forceinline__ void add_fixed64(uint64_t* p, float x) {
 }
 
 template <bool MIRROR>
-__global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRun run,
-                                                            ViewBatch vb, TileShape ts,
-                                                            const float* __restrict__ vol,
-                                                            float* __restrict__ q,
-                                                            int64_t vstride, float scale,
-                                                            int fixed_sums) {
+__device__ __forceinline__ void fp_tiled_body(GeoConst gc, SliceRun run, ViewBatch vb,
+                                              TileShape ts, const float* __restrict__ vol,
+                                              float* __restrict__ q, int64_t vstride,
+                                              float scale, int fixed_sums) {
   extern __shared__ __attribute__((aligned(16))) int atile[];
   __shared__ BrickView bvs[kMaxViewsPerLaunch];
   __shared__ uint32_t hist[kMaxStageViews * kHistStride];
@@ -460,6 +458,31 @@ __global__ __launch_bounds__(kThreads) void fp_tiled_kernel(GeoConst gc, SliceRu
     }
     __syncthreads();
   }
+}
+
+template <bool MIRROR>
+__global__ void fp_tiled_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                                const float* __restrict__ vol, float* __restrict__ q,
+                                int64_t vstride, float scale, int fixed_sums);
+
+// Mirrored runs: six 256-thread workgroups per CU (80 VGPRs). The 64-bit
+// paths' code otherwise lifts the register count past it, and five
+// workgroups cost 11 % at 2048^3. (Held to 80 registers, the plain variant
+// spills inside its splat loops, so it keeps its count.)
+template <>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6)))
+void fp_tiled_kernel<true>(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                           const float* __restrict__ vol, float* __restrict__ q, int64_t vstride,
+                           float scale, int fixed_sums) {
+  fp_tiled_body<true>(gc, run, vb, ts, vol, q, vstride, scale, fixed_sums);
+}
+
+template <>
+__global__ __launch_bounds__(kThreads)
+void fp_tiled_kernel<false>(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,
+                            const float* __restrict__ vol, float* __restrict__ q, int64_t vstride,
+                            float scale, int fixed_sums) {
+  fp_tiled_body<false>(gc, run, vb, ts, vol, q, vstride, scale, fixed_sums);
 }
 
 template <bool MIRROR>
