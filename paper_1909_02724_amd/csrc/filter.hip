@@ -31,7 +31,7 @@ namespace fdk {
 namespace {
 
 constexpr int kFilterThreads = 256;
-constexpr int kFftMaxLog = 13;             // L <= 8192 complex points (139 KB of LDS)
+constexpr int kFftMaxLog = 13;             // L <= 8192 complex points (132 KiB of LDS)
 constexpr int64_t kFftMaxGroups = 2048;    // workgroups of an FFT launch
 constexpr int kDirectMaxNu = 256;          // below this the direct kernel is cheaper
 constexpr int kDirectMaxLds = 8192;        // widest row of the direct kernel (2 x 64 KB of LDS)
@@ -129,7 +129,9 @@ hipError_t raise_lds_limit(size_t bytes) {
 // kernel's support |m| < N), summation by parts gives, for a in [0, N),
 //   q(a) = sum_{n < N} g(a - n) y(n) - c g(a - N),
 // with y(n) = x(n) - x(n - 1) (x(-1) = 0) the first difference of the
-// weighted row x and c = x(N - 1) its last value. This is the factorisation
+// weighted row x and c = x(N - 1) its last value. Setting y(N) = -c (the
+// difference to x(N) = 0) folds the last term into the sum over n <= N.
+// This is the factorisation
 // of the ramp into a derivative and a Hilbert-type transform: |w| over
 // |1 - e^{-iw}| stays within a factor of about pi/2 of its mean, so g's
 // spectrum G is nearly flat. That is what allows FP32 transforms. The ramp
@@ -139,18 +141,21 @@ hipError_t raise_lds_limit(size_t bytes) {
 // projections of ellipsoid phantoms, 512 to 4096 pixels). y carries only
 // the row's variation and G weights every bin about equally, so FP32
 // transforms of y stay within a few FP32 roundings of the output (about
-// 1e-7). y is formed in FP64 from the FP32 row and FP64 weights and rounded
-// once; g comes from an FP64 scan.
+// 1e-7). y is formed in FP32 from the row's differences and the weight's
+// steps (see row_diff), never from x; g comes from an FP64 scan.
 //
 // Rows are zero-padded to a power of two L >= 2N: with y supported on
-// [0, N) and g on [-N, N), the circular convolution of length L equals the
-// linear one on the N outputs. Two rows travel as the real and imaginary
-// parts of one complex sequence: g is real, so
-// IFFT(FFT(a + i b) G) = (g * a) + i (g * b). The FFTs are radix-16 Stockham
-// passes over points held in registers, exchanged through LDS between
-// passes; the inverse transform is the forward one of the conjugate. Each
-// workgroup computes G and the correction's g(a - N) once and then loops
-// over row pairs.
+// [0, N] and g on [-N, N), the outputs a in [0, N) see the differences
+// a - n in [-N, N), whose images a - n +- L fall outside [-N, N): the
+// circular convolution of length L equals the linear one there. Two rows
+// travel as the real and imaginary parts of one complex sequence: g is real,
+// so IFFT(FFT(a + i b) G) = (g * a) + i (g * b). The FFTs are radix-16
+// Stockham passes over points held in registers, exchanged through LDS
+// between passes, with each pass's twiddles read from a table of its own
+// (FP64 values rounded once); the inverse transform is the forward one of
+// the conjugate. Each workgroup computes the twiddle tables and G once and
+// then loops over row pairs; each pair's loads are unconditional and all in
+// flight together.
 using cf = float2;
 
 template <int LOGL>
@@ -162,16 +167,24 @@ struct FftCfg {
   static constexpr int RR = 1 << (LOGL % 4);         // first-pass radix (1: none)
   static constexpr int NP = (RR > 1 ? 1 : 0) + LOGL / 4;  // passes
   static constexpr int BUF = L + L / 16;             // padded points per FFT
-  static constexpr int THI = L / 64;                 // twiddle table: W^(64 j), j < L/64
+  // Span of pass p's butterflies (p > 0): points W^(r k) apart, k its twiddle step.
+  static constexpr int ns(int p) { return p == 0 ? 1 : (RR > 1 ? RR : 16) << (4 * (p - 1)); }
+  // Twiddle tables: pass p > 0 reads W^(r j L / (16 NS)), r in [1, 16),
+  // j < NS, at entry tw_off(p) + (r - 1) NS + j; TW entries in all.
+  static constexpr int tw_off(int p) {
+    int off = 0;
+    for (int q = 1; q < p; ++q) off += 15 * ns(q);
+    return off;
+  }
+  static constexpr int TW = tw_off(NP);
 };
-constexpr int kTwLo = 64;                            // and W^i, i < 64
 
 template <int LOGL, int IP>
 struct PassCfg {
   using C = FftCfg<LOGL>;
   static constexpr bool kRR = C::RR > 1 && IP == 0;
   static constexpr int R = kRR ? C::RR : 16;
-  static constexpr int NS = IP == 0 ? 1 : (C::RR > 1 ? C::RR : 16) << (4 * (IP - 1));
+  static constexpr int NS = C::ns(IP);
   static constexpr int B = 16 / R;  // butterflies per thread
 };
 
@@ -231,32 +244,12 @@ __device__ __forceinline__ void dft_reg(cf* v) {
   for (int i = 0; i < N; ++i) v[i] = a[i];
 }
 
-// W^m, W = exp(-2 pi i / L), m < L: the product of two table entries.
-__device__ __forceinline__ cf twiddle(const cf* thi, const cf* tlo, int32_t m) {
-  return cmul(thi[m >> 6], tlo[m & (kTwLo - 1)]);
-}
-
-// v[r] *= W^(r k) for r in [1, 16): the base twiddles W^(k 2^b), b < 4,
-// from the table, the rest as products at most three deep.
-__device__ __forceinline__ void apply_twiddles(cf* v, const cf* thi, const cf* tlo, int32_t k) {
-  const cf w1 = twiddle(thi, tlo, k), w2 = twiddle(thi, tlo, 2 * k);
-  const cf w4 = twiddle(thi, tlo, 4 * k), w8 = twiddle(thi, tlo, 8 * k);
-  const cf w3 = cmul(w1, w2), w5 = cmul(w1, w4), w6 = cmul(w2, w4), w7 = cmul(w3, w4);
-  v[1] = cmul(v[1], w1);
-  v[2] = cmul(v[2], w2);
-  v[3] = cmul(v[3], w3);
-  v[4] = cmul(v[4], w4);
-  v[5] = cmul(v[5], w5);
-  v[6] = cmul(v[6], w6);
-  v[7] = cmul(v[7], w7);
-  v[8] = cmul(v[8], w8);
-  v[9] = cmul(v[9], cmul(w1, w8));
-  v[10] = cmul(v[10], cmul(w2, w8));
-  v[11] = cmul(v[11], cmul(w3, w8));
-  v[12] = cmul(v[12], cmul(w4, w8));
-  v[13] = cmul(v[13], cmul(w5, w8));
-  v[14] = cmul(v[14], cmul(w6, w8));
-  v[15] = cmul(v[15], cmul(w7, w8));
+// v[r] *= W^(r k) for r in [1, 16), read from the pass's table (NS
+// entries per r; the thread's j = t mod NS picks k = j L / (16 NS)).
+template <int NS>
+__device__ __forceinline__ void apply_twiddles(cf* v, const cf* tab, int32_t j) {
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tab[(r - 1) * NS + j]);
 }
 
 // Input index of point (m, r) of pass IP for thread t: butterfly
@@ -289,10 +282,10 @@ __device__ __forceinline__ constexpr int last_of_first(int i) {
 // NS > 1 are radix 16 with one butterfly per thread (j = t), twiddle
 // exponent k = (t mod NS) L / (16 NS).
 template <int LOGL, int IP>
-__device__ __forceinline__ void pass_compute(cf* v, int32_t t, const cf* thi, const cf* tlo) {
+__device__ __forceinline__ void pass_compute(cf* v, int32_t t, const cf* tw) {
   using P = PassCfg<LOGL, IP>;
   if constexpr (P::NS > 1)
-    apply_twiddles(v, thi, tlo, (t % P::NS) * (FftCfg<LOGL>::L / (16 * P::NS)));
+    apply_twiddles<P::NS>(v, tw + FftCfg<LOGL>::tw_off(IP), t % P::NS);
 #pragma unroll
   for (int m = 0; m < P::B; ++m) dft_reg<P::R>(v + m * P::R);
 }
@@ -321,34 +314,33 @@ __device__ __forceinline__ void pass_gather_lds(const cf* buf, int32_t t, cf* v)
 // scatter_index; every earlier pass crosses LDS, behind a barrier that also
 // orders it after the buffer's previous reads.
 template <int LOGL, int IP>
-__device__ __forceinline__ void fft_rest(cf* buf, int32_t t, cf* v, const cf* thi, const cf* tlo) {
-  pass_compute<LOGL, IP>(v, t, thi, tlo);
+__device__ __forceinline__ void fft_rest(cf* buf, int32_t t, cf* v, const cf* tw) {
+  pass_compute<LOGL, IP>(v, t, tw);
   if constexpr (IP + 1 < FftCfg<LOGL>::NP) {
     __syncthreads();
     pass_scatter_lds<LOGL, IP>(buf, t, v);
     __syncthreads();
     pass_gather_lds<LOGL, IP + 1>(buf, t, v);
-    fft_rest<LOGL, IP + 1>(buf, t, v, thi, tlo);
+    fft_rest<LOGL, IP + 1>(buf, t, v, tw);
   }
 }
 
-// Cosine weight of pixel a on a row: D / sqrt(D^2 + ((b - cv) dv)^2 + ((a - cu) du)^2),
-// the row's share precomputed; an FP32 reciprocal square root refined by
-// one Newton step in FP64.
+// Cosine weight of pixel a on a row, w(a) = D / sqrt(D^2 + ((b - cv) dv)^2 +
+// ((a - cu) du)^2), in FP32: the row's share `base` comes from FP64, the
+// reciprocal square root from the hardware (within 1 ulp).
 struct RowWeight {
-  double d, base;
+  float base;  // D^2 + ((b - cv) dv)^2
+};
+struct ColConst {
+  float cu, du, d, mddu;  // cu, du, D, and -D du
 };
 __device__ __forceinline__ RowWeight row_weight(const GeoConst& gc, double dv, double sdd, int32_t b) {
   const double bb = (b - gc.cv) * dv;
-  const double d2 = sdd * sdd;
-  return RowWeight{sdd, fma(bb, bb, d2)};
+  return RowWeight{static_cast<float>(fma(bb, bb, sdd * sdd))};
 }
-__device__ __forceinline__ double pixel_weight(RowWeight rw, double cu, double du, int32_t a) {
-  const double x = (static_cast<double>(a) - cu) * du;
-  const double s = fma(x, x, rw.base);
-  const double r0 = static_cast<double>(__frsqrt_rn(static_cast<float>(s)));
-  const double r1 = r0 * fma(-0.5 * s, r0 * r0, 1.5);
-  return rw.d * r1;
+__device__ __forceinline__ float pixel_weight(RowWeight rw, const ColConst& cc, int32_t a) {
+  const float x = (static_cast<float>(a) - cc.cu) * cc.du;
+  return cc.d * __builtin_amdgcn_rsqf(fmaf(x, x, rw.base));
 }
 
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer descriptor, gfx9 family
@@ -376,20 +368,29 @@ __device__ __forceinline__ void buf_store_q(float x, __amdgpu_buffer_rsrc_t r, u
   __builtin_amdgcn_raw_buffer_store_b16(h.bits, r, off, 0, 0);
 }
 
-// First difference of the weighted row at pixel n < N (FP64, rounded once):
-// x(n) - x(n - 1), x(a) = e(a) w(a) (the adjoint leaves the row unweighted).
-// The load at n - 1 for n = 0 wraps to an out-of-range offset and reads 0.
+// First difference y(n) = x(n) - x(n - 1) of the weighted row x(a) = e(a) w(a)
+// at pixel n (x(-1) = 0, and x(a) = 0 for a >= N: pixels there read as zero;
+// the adjoint leaves the row unweighted), in FP32 without forming x:
+// y(n) = (e(n) - e(n - 1)) w(n) + e(n - 1) dw(n),
+// where the weight step dw(n) = w(n) - w(n - 1) comes from the identity
+// r1 - r0 = (s0 - s1) r0^2 r1^2 / (r0 + r1) for r = s^(-1/2), with
+// s0 - s1 = -du (x0 + x1) exact up to rounding. Each term then carries
+// rounding relative to the row's variation, not to x itself, which is what
+// the FP32 transforms of y need (see the FFT path above). The load at n - 1
+// for n = 0 wraps to an out-of-range offset and reads 0.
 template <bool ADJ>
-__device__ __forceinline__ float row_diff(__amdgpu_buffer_rsrc_t r, RowWeight rw, double cu,
-                                          double du, int32_t n) {
+__device__ __forceinline__ float row_diff(__amdgpu_buffer_rsrc_t r, RowWeight rw, const ColConst& cc,
+                                          int32_t n) {
   const uint32_t off = static_cast<uint32_t>(n) * 4u;
-  const double e0 = buf_load_f32(r, off), e1 = buf_load_f32(r, off - 4u);
-  if (ADJ) return static_cast<float>(e0 - e1);
-  // Separate statements: neither product fuses into the difference, so
-  // every instantiation rounds the same way.
-  const double x0 = e0 * pixel_weight(rw, cu, du, n);
-  const double x1 = e1 * pixel_weight(rw, cu, du, n - 1);
-  return static_cast<float>(x0 - x1);
+  const float e1 = buf_load_f32(r, off), e0 = buf_load_f32(r, off - 4u);
+  if (ADJ) return e1 - e0;
+  const float x1 = (static_cast<float>(n) - cc.cu) * cc.du;
+  const float x0 = x1 - cc.du;
+  const float r1 = __builtin_amdgcn_rsqf(fmaf(x1, x1, rw.base));
+  const float r0 = __builtin_amdgcn_rsqf(fmaf(x0, x0, rw.base));
+  const float p = r0 * r1;
+  const float dw = (x1 + x0) * cc.mddu * (p * p) * __builtin_amdgcn_rcpf(r0 + r1);
+  return fmaf(e1 - e0, cc.d * r1, e0 * dw);
 }
 
 template <int LOGL, typename OutT, bool ADJ>
@@ -402,16 +403,19 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
   const int32_t g = static_cast<int32_t>(threadIdx.x) / C::TPF;
   const int32_t t = static_cast<int32_t>(threadIdx.x) % C::TPF;
   cf* buf = fbuf + g * C::BUF;
-  cf* thi = fbuf + C::G * C::BUF;  // twiddle tables after the FFT buffers
-  cf* tlo = thi + C::THI;
+  cf* tw = fbuf + C::G * C::BUF;  // twiddle tables after the FFT buffers
   const int32_t nu = gc.nu;
-  const double cu = gc.cu;
+  const ColConst cc{static_cast<float>(gc.cu), static_cast<float>(du), static_cast<float>(sdd),
+                    static_cast<float>(-sdd * du)};
 
-  for (int32_t i = threadIdx.x; i < C::THI + kTwLo; i += C::WG) {
-    const int32_t m = i < C::THI ? 64 * i : i - C::THI;
+  for (int32_t i = threadIdx.x; i < C::TW; i += C::WG) {
+    int p = 1;
+    while (p + 1 < C::NP && i >= C::tw_off(p + 1)) ++p;
+    const int32_t ns = C::ns(p), rel = i - C::tw_off(p);
+    const int32_t m = (rel / ns + 1) * (rel % ns) * (C::L / (16 * ns));  // < L
     double sv, cv;
     sincospi(-2.0 * static_cast<double>(m) / C::L, &sv, &cv);
-    thi[i] = make_float2(static_cast<float>(cv), static_cast<float>(sv));  // tlo follows thi
+    tw[i] = make_float2(static_cast<float>(cv), static_cast<float>(sv));
   }
 
   // g(m) for m in [-N, N), FP64, at dg[m + N]: an inclusive scan of the
@@ -449,8 +453,7 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
   }
 
   // G: FFT of g placed circularly (index m mod L). Each thread keeps
-  // conj(G) / L at the points it gathers in a transform's first pass, and
-  // g(n - N) at its output pixels n = t + j TPF, j < 8.
+  // conj(G) / L at the points it gathers in a transform's first pass.
   cf v[16];
 #pragma unroll
   for (int m = 0; m < B0; ++m)
@@ -461,13 +464,7 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
       const float gv = (s >= -nu && s < nu) ? static_cast<float>(dg[s + nu]) : 0.0f;
       v[m * R0 + r] = make_float2(gv, 0.0f);
     }
-  float gend[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int32_t n = t + j * C::TPF;
-    gend[j] = n < nu ? static_cast<float>(dg[n]) : 0.0f;
-  }
-  fft_rest<LOGL, 0>(buf, t, v, thi, tlo);  // its first barrier follows every read of dg
+  fft_rest<LOGL, 0>(buf, t, v, tw);  // its first barrier follows every read of dg
   cf gc_[16];
   {
     constexpr float inv_l = 1.0f / static_cast<float>(C::L);  // a power of two: exact
@@ -498,29 +495,29 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
     const __amdgpu_buffer_rsrc_t ia = row_rsrc(e + (has_a ? rowa_in : 0), has_a ? nu * 4u : 0u);
     const __amdgpu_buffer_rsrc_t ib = row_rsrc(e + (has_b ? rowb_in : 0), has_b ? nu * 4u : 0u);
     const RowWeight wa = row_weight(gc, dv, sdd, ba), wb = row_weight(gc, dv, sdd, bb);
-    // c = x(N - 1), the last weighted pixel of each row.
-    const uint32_t last = static_cast<uint32_t>(nu - 1) * 4u;
-    double ca = buf_load_f32(ia, last), cb = buf_load_f32(ib, last);
-    if (!ADJ) {
-      ca *= pixel_weight(wa, cu, du, nu - 1);
-      cb *= pixel_weight(wb, cu, du, nu - 1);
-    }
-
-    // Forward transform of y; points at or beyond N (the upper half and
-    // more) are zero.
+    // Forward transform of y over [0, N] and zeros beyond. The loads are
+    // unconditional, all in flight together: pixels at or beyond N read as
+    // zero, so row_diff gives 0 past N and, at N, y(N) = -x(N - 1) =
+    // -c (up to rounding). Points below L/2 are those of registers
+    // r < R0/2; N <= L/2 can only fall at r = R0/2 when N = L/2, on thread
+    // 0's first butterfly.
 #pragma unroll
     for (int m = 0; m < B0; ++m)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         float re = 0.0f, im = 0.0f;
-        const int32_t n = gather_index<LOGL, 0>(t, m, r);
-        if (r < R0 / 2 && n < nu) {
-          re = row_diff<ADJ>(ia, wa, cu, du, n);
-          im = row_diff<ADJ>(ib, wb, cu, du, n);
+        if (r < R0 / 2) {
+          const int32_t n = gather_index<LOGL, 0>(t, m, r);
+          re = row_diff<ADJ>(ia, wa, cc, n);
+          im = row_diff<ADJ>(ib, wb, cc, n);
         }
         v[m * R0 + r] = make_float2(re, im);
       }
-    fft_rest<LOGL, 0>(buf, t, v, thi, tlo);
+    if (nu == C::L / 2) {
+      const int32_t n = gather_index<LOGL, 0>(t, 0, R0 / 2);
+      v[R0 / 2] = make_float2(row_diff<ADJ>(ia, wa, cc, n), row_diff<ADJ>(ib, wb, cc, n));
+    }
+    fft_rest<LOGL, 0>(buf, t, v, tw);
     // Inverse: the forward transform of conj(Y G) / L, taken in registers
     // (the last pass's points are the first pass's).
     cf z[16];
@@ -529,7 +526,7 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
       const cf y = v[last_of_first<LOGL>(i)];
       z[i] = cmul(make_float2(y.x, -y.y), gc_[i]);
     }
-    fft_rest<LOGL, 0>(buf, t, z, thi, tlo);
+    fft_rest<LOGL, 0>(buf, t, z, tw);
     // The last pass has one radix-16 butterfly per thread (j = t, NS = L/16):
     // result j is point t + j L/16, so the stores are coalesced; only the
     // lower half (j < 8) holds row pixels.
@@ -537,18 +534,18 @@ __global__ __launch_bounds__(FftCfg<LOGL>::WG) void filter_fft_kernel(
         row_rsrc(q + (has_a ? rowa_out : 0), has_a ? nu * static_cast<uint32_t>(sizeof(OutT)) : 0u);
     const __amdgpu_buffer_rsrc_t ob =
         row_rsrc(q + (has_b ? rowb_out : 0), has_b ? nu * static_cast<uint32_t>(sizeof(OutT)) : 0u);
-    const float fca = static_cast<float>(ca), fcb = static_cast<float>(cb);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int32_t n = t + j * C::TPF;
-      float ya = fmaf(-fca, gend[j], z[j].x), yb = fmaf(-fcb, gend[j], -z[j].y);
+      float ya = z[j].x, yb = -z[j].y;
       if (ADJ) {
-        ya = static_cast<float>(ya * pixel_weight(wa, cu, du, n));
-        yb = static_cast<float>(yb * pixel_weight(wb, cu, du, n));
+        ya *= pixel_weight(wa, cc, n);
+        yb *= pixel_weight(wb, cc, n);
       }
       // The FP32 result is rounded as such before any 16-bit store: without
-      // the barrier the FMA fuses into a mixed-precision one that rounds once
-      // to 16 bits, which can differ from the FP32 output rounded.
+      // the barrier the last operation could fuse into a mixed-precision one
+      // that rounds once to 16 bits, which can differ from the FP32 output
+      // rounded.
       asm volatile("" : "+v"(ya), "+v"(yb));
       const uint32_t off = static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(OutT));
       buf_store_q(ya, oa, off, static_cast<OutT*>(nullptr));
@@ -561,13 +558,13 @@ template <int LOGL, typename OutT, bool ADJ>
 int launch_fft(const GeoConst& gc, const RowBand& rb, double du, double dv, double sdd, double tau,
                int kind, int64_t nrows, const float* e, OutT* q, hipStream_t st) {
   using C = FftCfg<LOGL>;
-  const size_t lds = (static_cast<size_t>(C::G) * C::BUF + C::THI + kTwLo) * sizeof(cf);
+  const size_t lds = (static_cast<size_t>(C::G) * C::BUF + C::TW) * sizeof(cf);
   auto kern = &filter_fft_kernel<LOGL, OutT, ADJ>;
   if (lds > 65536) {
     const hipError_t err = raise_lds_limit<&filter_fft_kernel<LOGL, OutT, ADJ>>(lds);
     if (err != hipSuccess) return static_cast<int>(err);
   }
-  // Workgroups loop over row pairs (H is computed once per workgroup): a
+  // Workgroups loop over row pairs (G is computed once per workgroup): a
   // few per CU at most.
   const int64_t npairs = (nrows + 1) / 2;
   const int64_t want = (npairs + C::G - 1) / C::G;

@@ -389,7 +389,7 @@ def test_bp_edge_geometries(name):
     assert rel_l2(fp, fref) <= 1e-5
 
 
-@pytest.mark.parametrize("nu", [257, 300, 512, 513, 1000, 2048, 4096])
+@pytest.mark.parametrize("nu", [257, 300, 512, 513, 1000, 1024, 2048, 4096])
 @pytest.mark.parametrize("kind", ["ramlak", "shepp-logan"])
 def test_filter_fft_path_matches_oracle(nu, kind):
     """Rows above 256 pixels take the FFT path: 257-512 pixels 1024-point
