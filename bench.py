@@ -4,7 +4,7 @@
     python bench.py [--steps K] [--warmup W] [--workload bp2048|slab4096]
 
 Workload (default): 2048^3 FP32 volume, 2048 views of 2048^2 pixels over a
-full circle, views in launches of 32. A step is one complete back-projection
+full circle, views in launches of 64. A step is one complete back-projection
 of all 2048 views into the volume (every voxel x view update, 2^44 of them),
 with the filtered projections already resident in HBM. GUPS is
 Nx*Ny*Nz*Np / (T * 2^30), T the kernel time of the step, measured with HIP
@@ -24,7 +24,7 @@ of 128-slice slabs at the volume's top and bottom (16 GiB), from 4096 views
 of 4096^2 pixels streamed in 16-view FP16 chunks: the noisy 64-ellipsoid
 line integrals (noise 1%) of the slab's detector row bands are generated
 into HBM first (untimed); then a producer stream filters them chunk by chunk
-into FP16 buffers while the previous 32 views (two chunks) back-project. A step is one pass over all 4096 views; GUPS counts
+into FP16 buffers while the previous 64 views (four chunks) back-project. A step is one pass over all 4096 views; GUPS counts
 the back-projection launches' event time (the rate the paper reports) and,
 beside it, the whole pipeline's wall time. The default run adds one such
 pass to its line (--no-slab skips it), and the time of a SIRT iteration
@@ -79,9 +79,13 @@ LDS_BYTES_PER_UPDATE = 16.0  # 4 FP32 taps (value and u-difference of two rows)
 ADJ_VALU_OPS_PER_UPDATE = 24.5
 ADJ_LDS_BYTES_PER_UPDATE = 16.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "bp_tiled_mirror_kernel_bp2048_traffic.json")
-# Slab workload: views are filtered in 16-view chunks; two contiguous chunks
-# make one back-projection launch (the volume is read and written per launch).
-SLAB_VIEWS_PER_LAUNCH = 32
+# Views per launch of the library's back-projector and adjoint (the volume
+# is read and written once per launch).
+BP_VIEWS_PER_LAUNCH = 64
+ADJ_VIEWS_PER_LAUNCH = 32
+# Slab workload: views are filtered in 16-view chunks; four contiguous chunks
+# make one back-projection launch.
+SLAB_VIEWS_PER_LAUNCH = 64
 
 
 def profiled_counters(workload):
@@ -543,7 +547,7 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     updates = float(g.nx) * g.ny * g.nz * n_views
-    launches = math.ceil(n_views / 32)
+    launches = math.ceil(n_views / BP_VIEWS_PER_LAUNCH)
     log(f"workload {args.workload}: {g.nx}x{g.ny}x{g.nz} volume, {n_views} views of {g.nv}x{g.nu}")
     if args.copy_calibration:
         n = args.copy_calibration * 2 ** 18
@@ -591,11 +595,12 @@ def main():
         return sum(ms) / len(ms)
 
     # Accuracy of each storage leg against the FP64 oracle: the same kernel
-    # and launch shape on a subset of the views (8 launches of 32 consecutive
+    # and launch shape on a subset of the views (4 launches of 64 consecutive
     # views at starting angles spread over the circle), sampled voxels.
     n_acc = min(256, n_views)
-    acc_views = np.concatenate([np.arange(s0, s0 + 32) for s0 in
-                                np.linspace(0, n_views - 32, n_acc // 32).astype(int)])
+    nb = BP_VIEWS_PER_LAUNCH
+    acc_views = np.concatenate([np.arange(s0, s0 + nb) for s0 in
+                                np.linspace(0, n_views - nb, n_acc // nb).astype(int)])
     acc_ang = np.ascontiguousarray(ang[acc_views])
     acc_vox = synth.sample_voxels(211, g, 16384, columns=4)
     acc_idx = torch.from_numpy(acc_vox).to(dev)
@@ -622,7 +627,7 @@ def main():
             result_extra[f"{name}_store_gups"] = round(gups(updates, ms16 / 1e3), 2)
             result_extra[f"{name}_ms_per_step"] = round(ms16, 2)
             result_extra[f"{name}_roofline"] = {
-                k: v for k, v in roofline_of(ms16, launches, updates, g, 32, 2.0,
+                k: v for k, v in roofline_of(ms16, launches, updates, g, BP_VIEWS_PER_LAUNCH, 2.0,
                                              f"bp_tiled_mirror_kernel<{name}_t>", None).items()
                 if k not in ("traffic", "traffic_unit", "hbm_achieved_GBps",
                              "traffic_over_algorithmic")}
@@ -642,8 +647,8 @@ def main():
             log(f"{label}: rel-L2 {err:.3e} against the FP64 oracle (FP32 inputs), "
                 f"{len(acc_vox)} sampled voxels x {n_acc} views")
         result_extra["rel_l2_sample"] = (f"{len(acc_vox)} voxels (seed 211, 4 full z-columns) x "
-                                         f"{n_acc} views (8 launches of 32 spread over the "
-                                         f"circle), oracle fed the FP32 projections")
+                                         f"{n_acc} views ({n_acc // nb} launches of {nb} spread "
+                                         f"over the circle), oracle fed the FP32 projections")
         log(f"oracle comparison in {time.time() - t_acc:.1f} s")
 
     if not args.no_adjoint:
@@ -670,7 +675,8 @@ def main():
         result_extra["adjoint_views_timed"] = nv_adj
         result_extra["adjoint_reps"] = reps
         result_extra["adjoint_roofline"] = {
-            k: v for k, v in roofline_of(msa, math.ceil(nv_adj / 32), ua, g, 32, 4.0,
+            k: v for k, v in roofline_of(msa, math.ceil(nv_adj / ADJ_VIEWS_PER_LAUNCH), ua, g,
+                                         ADJ_VIEWS_PER_LAUNCH, 4.0,
                                          "fp_tiled_kernel<true>", None,
                                          valu_ops=ADJ_VALU_OPS_PER_UPDATE,
                                          lds_bytes=ADJ_LDS_BYTES_PER_UPDATE,
@@ -682,7 +688,8 @@ def main():
 
     # ---- roofline of the dominant kernel (the back-projection launches) ----
     traffic, valu_insts = profiled_counters(args.workload)
-    roofline = roofline_of(ms32, launches, updates, g, 32, 4.0, "bp_tiled_mirror_kernel<float>",
+    roofline = roofline_of(ms32, launches, updates, g, BP_VIEWS_PER_LAUNCH, 4.0,
+                           "bp_tiled_mirror_kernel<float>",
                            traffic, valu_insts)
 
     if not args.no_sirt and args.workload == "bp2048":
@@ -769,9 +776,9 @@ def main():
         "data": "synthetic: seeded 32-ellipsoid phantom, analytic line integrals, "
                 "Shepp-Logan filtered on the GPU",
         "config": {"workload": f"{args.workload}: {g.nx}x{g.ny}x{g.nz} FP32 volume, "
-                               f"{n_views} views of {g.nv}x{g.nu}, 32 views per launch",
+                               f"{n_views} views of {g.nv}x{g.nu}, {BP_VIEWS_PER_LAUNCH} views per launch",
                    "nx": g.nx, "ny": g.ny, "nz": g.nz, "n_views": n_views, "nu": g.nu,
-                   "nv": g.nv, "views_per_launch": 32},
+                   "nv": g.nv, "views_per_launch": BP_VIEWS_PER_LAUNCH},
         **result_extra,
         "roofline": roofline,
         "cpu_baseline": cpu,

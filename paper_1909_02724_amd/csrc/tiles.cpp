@@ -69,7 +69,7 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
     ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
     return ts;
   }
-  // Back-projector: the five-wave kernel (slots prefetch slots, 30 KB of
+  // Back-projector: the five-wave kernel (slots prefetch slots, 29 KB of
   // tiles) when it stages all kBpStageViews views per stage, else the
   // four-wave one (more slots and 36 KB) if that stages more.
   const int64_t vc5 = std::min<int64_t>({kBpStageViews, kBpTileLdsBytes / per_view, slots / ts.rows});
