@@ -80,9 +80,9 @@ ADJ_VALU_OPS_PER_UPDATE = 24.5
 ADJ_LDS_BYTES_PER_UPDATE = 16.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "bp_tiled_mirror_kernel_bp2048_traffic.json")
 # Views per launch of the library's back-projector and adjoint (the volume
-# is read and written once per launch).
+# is read, and written, once per launch).
 BP_VIEWS_PER_LAUNCH = 64
-ADJ_VIEWS_PER_LAUNCH = 32
+ADJ_VIEWS_PER_LAUNCH = 64
 # Slab workload: views are filtered in 16-view chunks; four contiguous chunks
 # make one back-projection launch.
 SLAB_VIEWS_PER_LAUNCH = 64

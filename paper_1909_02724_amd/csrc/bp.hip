@@ -387,7 +387,7 @@ void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape t
                             const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
                             float scale, int accumulate) {
   extern __shared__ float4 tile[];
-  __shared__ BrickView bvs[kBpViewsPerLaunch];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
   bp_brick_body<T, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
 }
 
@@ -397,7 +397,7 @@ void bp_tiled_mirror_wide_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileSh
                                  const T* __restrict__ q, int64_t vstride,
                                  float* __restrict__ vol, float scale, int accumulate) {
   extern __shared__ float4 tile[];
-  __shared__ BrickView bvs[kBpViewsPerLaunch];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
   bp_brick_body<T, true, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile,
                                      bvs);
 }
@@ -408,7 +408,7 @@ void bp_tiled_plain_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts
                            const T* __restrict__ q, int64_t vstride, float* __restrict__ vol,
                            float scale, int accumulate) {
   extern __shared__ float4 tile[];
-  __shared__ BrickView bvs[kBpViewsPerLaunch];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
   bp_brick_body<T, false, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile, bvs);
 }
 
@@ -418,7 +418,7 @@ void bp_tiled_plain_wide_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileSha
                                 const T* __restrict__ q, int64_t vstride,
                                 float* __restrict__ vol, float scale, int accumulate) {
   extern __shared__ float4 tile[];
-  __shared__ BrickView bvs[kBpViewsPerLaunch];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
   bp_brick_body<T, false, true, true>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, tile,
                                       bvs);
 }
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(kThreads) void bp_direct_kernel(GeoConst gc, SliceR
                                                              int64_t vstride,
                                                              float* __restrict__ vol, float scale,
                                                              int accumulate) {
-  __shared__ BrickView bvs[kBpViewsPerLaunch];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
   bp_brick_body<T, MIRROR, false>(gc, run, vb, ts, q, vstride, vol, scale, accumulate, nullptr,
                                   bvs);
 }

@@ -320,8 +320,8 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
   }
   const int64_t vstride = (int64_t)g->nu * g->nv;
   fdk::ViewBatch vb;
-  for (int32_t b = 0; b < nviews; b += fdk::kBpViewsPerLaunch) {
-    vb.nviews = std::min(fdk::kBpViewsPerLaunch, nviews - b);
+  for (int32_t b = 0; b < nviews; b += fdk::kMaxViewsPerLaunch) {
+    vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
     for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
     const char* qb = static_cast<const char*>(q) + (size_t)b * vstride * dtype_size(q_dtype);
     for (const fdk::SliceRun& r : sl.runs) {
@@ -362,8 +362,8 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
       return fail(FDK_ERR_HIP, "zero fill failed: HIP error %d", e);
   }
   fdk::ViewBatch vb;
-  for (int32_t b = 0; b < nviews; b += fdk::kFpViewsPerLaunch) {
-    vb.nviews = std::min(fdk::kFpViewsPerLaunch, nviews - b);
+  for (int32_t b = 0; b < nviews; b += fdk::kMaxViewsPerLaunch) {
+    vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
     for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
     for (const fdk::SliceRun& r : sl.runs) {
       // Plain runs: 32-slice bricks and a single accumulation plane; their

@@ -10,12 +10,11 @@ namespace fdk {
 
 // Views per kernel launch: the per-view constants travel in the kernel
 // argument block (48 bytes a view, within its 4 KB), and each launch reads
-// and writes the volume once. The back-projector takes 64 views a launch
-// (measured at 2048^3: 6 % faster than 32, which read and wrote the volume
-// twice as often); the adjoint keeps 32, its workgroups holding more LDS.
+// (and for the back-projector writes) the volume once and sets up each
+// brick once. Measured against 32 views a launch: the back-projector 6 %
+// faster at 2048^3, the adjoint 2 % at 2048^3 and 10 % at 256^3 from 360
+// views.
 constexpr int kMaxViewsPerLaunch = 64;
-constexpr int kBpViewsPerLaunch = 64;
-constexpr int kFpViewsPerLaunch = 32;
 
 // Per-view geometry in the reduced-cost form of Alg. 4, evaluated in FP64 on
 // the host from the view angle (Eq. 2 expanded):

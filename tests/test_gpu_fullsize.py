@@ -117,7 +117,7 @@ def test_bp2048_full_size_sampled():
 @pytest.mark.parametrize("off_v,nviews", [(0.0, 256), (0.27, 64)], ids=["mirrored", "plain"])
 def test_adjoint_2048_dot_full_size(off_v, nviews):
     """The adjoint in the benchmark's adjoint configuration (2048^3, 256
-    views of 2048^2 spread over the circle, 32 views per launch), and on
+    views of 2048^2 spread over the circle, 64 views per launch), and on
     plain slice runs (off_v = 0.27: no pixel-aligned mirror, 32-slice
     bricks): <B q, x> = <q, F x> on positive data to 1e-6 relative, inner
     products in FP64 slab by slab. B is pinned to the oracle at this size by
