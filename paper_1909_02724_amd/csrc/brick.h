@@ -167,8 +167,8 @@ struct BrickCoords {
 // linear order that runs over z-segments outermost and, within a segment,
 // over bands of kBandRows brick rows, column by column. The workgroups an
 // XCD holds at once (32 CUs x 4) then form a compact patch of bricks, about
-// 16 x 8, whose detector footprints in all the views of a launch fit its L2
-// together (a row of bricks across the volume would not).
+// 16 x 8, whose detector footprints overlap from brick to brick, so that its
+// L2 serves most of their taps (a row of bricks across the volume did not).
 constexpr uint32_t kBandRows = 8;
 __device__ __forceinline__ void brick_index(const TileShape& ts, int32_t* bx, int32_t* by,
                                             int32_t* seg) {
