@@ -131,10 +131,9 @@ hipError_t raise_lds_limit(size_t bytes) {
 // with y(n) = x(n) - x(n - 1) (x(-1) = 0) the first difference of the
 // weighted row x and c = x(N - 1) its last value. Setting y(N) = -c (the
 // difference to x(N) = 0) folds the last term into the sum over n <= N.
-// This is the factorisation
-// of the ramp into a derivative and a Hilbert-type transform: |w| over
-// |1 - e^{-iw}| stays within a factor of about pi/2 of its mean, so g's
-// spectrum G is nearly flat. That is what allows FP32 transforms. The ramp
+// This is the factorisation of the ramp into a derivative and a
+// Hilbert-type transform: |w| over |1 - e^{-iw}| stays within a factor of
+// about pi/2 of its mean, so g's spectrum G is nearly flat. That is what allows FP32 transforms. The ramp
 // removes most of a smooth row's content: transformed directly, the FP32
 // rounding of its large low-frequency terms spreads over all bins, which
 // the ramp then amplifies (1e-6 to 2e-5 rel-L2 off the FP64 result on
@@ -167,7 +166,8 @@ struct FftCfg {
   static constexpr int RR = 1 << (LOGL % 4);         // first-pass radix (1: none)
   static constexpr int NP = (RR > 1 ? 1 : 0) + LOGL / 4;  // passes
   static constexpr int BUF = L + L / 16;             // padded points per FFT
-  // Span of pass p's butterflies (p > 0): points W^(r k) apart, k its twiddle step.
+  // Stride NS of pass p: the length of the sub-transforms its inputs come
+  // from (1 for the first pass, then the product of the earlier radices).
   static constexpr int ns(int p) { return p == 0 ? 1 : (RR > 1 ? RR : 16) << (4 * (p - 1)); }
   // Twiddle tables: pass p > 0 reads W^(r j L / (16 NS)), r in [1, 16),
   // j < NS, at entry tw_off(p) + (r - 1) NS + j; TW entries in all.
