@@ -194,6 +194,31 @@ def test_accumulate_and_zero_views():
     assert rel_l2(host(a), host(b)) <= 1e-6
 
 
+@pytest.mark.parametrize("off_v", [0.0, 0.3], ids=["mirrored", "plain"])
+def test_several_launches_with_a_ragged_last_one(off_v):
+    """150 views take three launches of the back-projector and the adjoint
+    (64 + 64 + 22 views): the first launch writes the volume (or zeroes the
+    projections), the later ones add to it. Both against the oracle, with
+    and without accumulating into existing data."""
+    g = BASE.replace(off_v=off_v)
+    n = 150
+    ang = synth.angles(n, start=0.1)
+    q = synth.random_projections(17, n, g)
+    ref = oracle.backproject(g, ang, q.astype(np.float64), scale=0.7)
+    got = host(fdk.backproject(gpu(q), g, ang, scale=0.7))
+    assert rel_l2(got, ref) <= 1e-5
+    base = np.random.default_rng(18).standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
+    out = gpu(base)
+    fdk.backproject(gpu(q), g, ang, out=out, accumulate=True, scale=0.7)
+    assert rel_l2(host(out), base + ref) <= 1e-5
+    x = np.random.default_rng(19).standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
+    fref = oracle.forward_project(g, ang, x.astype(np.float64), scale=0.7)
+    fp = host(fdk.forward_project(gpu(x), g, ang, scale=0.7))
+    err = rel_l2(fp, fref)
+    announce(f"  150 views off_v={off_v}: back-projection and adjoint vs oracle, adjoint {err:.3e}")
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("variant", ["tiled", "direct", "magnified"])
 @pytest.mark.parametrize("dtype,rnd", [(torch.float16, "f16"), (torch.bfloat16, "bf16")])
 def test_bp_16bit_storage(dtype, rnd, variant):
