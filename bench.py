@@ -4,7 +4,7 @@
     python bench.py [--steps K] [--warmup W] [--workload bp2048|slab4096]
 
 Workload (default): 2048^3 FP32 volume, 2048 views of 2048^2 pixels over a
-full circle, views in launches of 64. A step is one complete back-projection
+full circle, in 22 launches of 93 or 94 views. A step is one complete back-projection
 of all 2048 views into the volume (every voxel x view update, 2^44 of them),
 with the filtered projections already resident in HBM. GUPS is
 Nx*Ny*Nz*Np / (T * 2^30), T the kernel time of the step, measured with HIP
@@ -24,7 +24,7 @@ of 128-slice slabs at the volume's top and bottom (16 GiB), from 4096 views
 of 4096^2 pixels streamed in 16-view FP16 chunks: the noisy 64-ellipsoid
 line integrals (noise 1%) of the slab's detector row bands are generated
 into HBM first (untimed); then a producer stream filters them chunk by chunk
-into FP16 buffers while the previous 64 views (four chunks) back-project. A step is one pass over all 4096 views; GUPS counts
+into FP16 buffers while the previous 96 views (six chunks) back-project. A step is one pass over all 4096 views; GUPS counts
 the back-projection launches' event time (the rate the paper reports) and,
 beside it, the whole pipeline's wall time. The default run adds one such
 pass to its line (--no-slab skips it), and the time of a SIRT iteration
@@ -79,13 +79,14 @@ LDS_BYTES_PER_UPDATE = 16.0  # 4 FP32 taps (value and u-difference of two rows)
 ADJ_VALU_OPS_PER_UPDATE = 24.5
 ADJ_LDS_BYTES_PER_UPDATE = 16.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "bp_tiled_mirror_kernel_bp2048_traffic.json")
-# Views per launch of the library's back-projector and adjoint (the volume
-# is read, and written, once per launch).
-BP_VIEWS_PER_LAUNCH = 64
+# Most views per launch of the library's back-projector and adjoint (the
+# volume is read, and written, once per launch); a call's views are split
+# evenly over the fewest launches.
+BP_VIEWS_PER_LAUNCH = 96
 ADJ_VIEWS_PER_LAUNCH = 64
-# Slab workload: views are filtered in 16-view chunks; four contiguous chunks
+# Slab workload: views are filtered in 16-view chunks; six contiguous chunks
 # make one back-projection launch.
-SLAB_VIEWS_PER_LAUNCH = 64
+SLAB_VIEWS_PER_LAUNCH = 96
 
 
 def profiled_counters(workload):
@@ -508,13 +509,13 @@ def main_slab(args):
                 "on a second stream while the previous launch back-projects",
         "config": {"workload": f"slab4096: {g.nx}x{g.ny}x{sl['nz_local']} FP32 mirror-pair slab "
                                f"of a {g.nz}^3 volume, {cfg['np']} views of {g.nv}x{g.nu} FP16 "
-                               f"filtered in chunks of {cfg['B']}, {SLAB_VIEWS_PER_LAUNCH} per launch",
+                               f"filtered in chunks of {cfg['B']}, up to {SLAB_VIEWS_PER_LAUNCH} per launch",
                    "nx": g.nx, "ny": g.ny, "nz_local": sl["nz_local"], "n_views": cfg["np"],
                    "nu": g.nu, "nv": g.nv, "chunk_views": cfg["B"],
                    "views_per_launch": SLAB_VIEWS_PER_LAUNCH},
         "pipeline_gups": round(gups(updates, wall_ms / 1e3), 2),
         "pipeline_ms_per_step": round(wall_ms, 2),
-        "roofline": roofline_of(bp_ms, launches, updates, g, SLAB_VIEWS_PER_LAUNCH, 2.0,
+        "roofline": roofline_of(bp_ms, launches, updates, g, cfg["np"] / launches, 2.0,
                                 "bp_tiled_mirror_kernel<f16_t>", None),
         "cpu_baseline": None,
     }
@@ -548,6 +549,7 @@ def main():
     stream = torch.cuda.current_stream(dev)
     updates = float(g.nx) * g.ny * g.nz * n_views
     launches = math.ceil(n_views / BP_VIEWS_PER_LAUNCH)
+    bp_vpl = n_views / launches  # views per launch, on average
     log(f"workload {args.workload}: {g.nx}x{g.ny}x{g.nz} volume, {n_views} views of {g.nv}x{g.nu}")
     if args.copy_calibration:
         n = args.copy_calibration * 2 ** 18
@@ -595,10 +597,10 @@ def main():
         return sum(ms) / len(ms)
 
     # Accuracy of each storage leg against the FP64 oracle: the same kernel
-    # and launch shape on a subset of the views (4 launches of 64 consecutive
+    # and launch shape on a subset of the views (3 launches of 96 consecutive
     # views at starting angles spread over the circle), sampled voxels.
-    n_acc = min(256, n_views)
     nb = BP_VIEWS_PER_LAUNCH
+    n_acc = min(3 * nb, n_views)
     acc_views = np.concatenate([np.arange(s0, s0 + nb) for s0 in
                                 np.linspace(0, n_views - nb, n_acc // nb).astype(int)])
     acc_ang = np.ascontiguousarray(ang[acc_views])
@@ -627,7 +629,7 @@ def main():
             result_extra[f"{name}_store_gups"] = round(gups(updates, ms16 / 1e3), 2)
             result_extra[f"{name}_ms_per_step"] = round(ms16, 2)
             result_extra[f"{name}_roofline"] = {
-                k: v for k, v in roofline_of(ms16, launches, updates, g, BP_VIEWS_PER_LAUNCH, 2.0,
+                k: v for k, v in roofline_of(ms16, launches, updates, g, bp_vpl, 2.0,
                                              f"bp_tiled_mirror_kernel<{name}_t>", None).items()
                 if k not in ("traffic", "traffic_unit", "hbm_achieved_GBps",
                              "traffic_over_algorithmic")}
@@ -688,7 +690,7 @@ def main():
 
     # ---- roofline of the dominant kernel (the back-projection launches) ----
     traffic, valu_insts = profiled_counters(args.workload)
-    roofline = roofline_of(ms32, launches, updates, g, BP_VIEWS_PER_LAUNCH, 4.0,
+    roofline = roofline_of(ms32, launches, updates, g, bp_vpl, 4.0,
                            "bp_tiled_mirror_kernel<float>",
                            traffic, valu_insts)
 
@@ -776,9 +778,10 @@ def main():
         "data": "synthetic: seeded 32-ellipsoid phantom, analytic line integrals, "
                 "Shepp-Logan filtered on the GPU",
         "config": {"workload": f"{args.workload}: {g.nx}x{g.ny}x{g.nz} FP32 volume, "
-                               f"{n_views} views of {g.nv}x{g.nu}, {BP_VIEWS_PER_LAUNCH} views per launch",
+                               f"{n_views} views of {g.nv}x{g.nu}, {launches} launches of at most "
+                               f"{BP_VIEWS_PER_LAUNCH} views",
                    "nx": g.nx, "ny": g.ny, "nz": g.nz, "n_views": n_views, "nu": g.nu,
-                   "nv": g.nv, "views_per_launch": BP_VIEWS_PER_LAUNCH},
+                   "nv": g.nv, "views_per_launch": round(bp_vpl, 2)},
         **result_extra,
         "roofline": roofline,
         "cpu_baseline": cpu,

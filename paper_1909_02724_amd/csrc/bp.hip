@@ -106,7 +106,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
   const float kvf = static_cast<float>(gc.kv);
 
   if (tid < vb.nviews)
-    bvs[tid] = brick_setup(gc, vb.view[tid], i_lo, i_hi, j_lo, j_hi, kb, ts.tu, ts.tv, BZ, MIRROR);
+    bvs[tid] = brick_setup(gc, view_geo(gc, vb.sn[tid], vb.cs[tid]), i_lo, i_hi, j_lo, j_hi, kb, ts.tu, ts.tv, BZ, MIRROR);
   __syncthreads();
 
   float acc[kBrickZ], accm[kBrickZ];
@@ -323,7 +323,7 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
     }
   } else {
     for (int32_t s = 0; s < vb.nviews; ++s) {
-      const ColumnF32 c = column_f64(gc, vb.view[s], bvs[s], i, j, kb);
+      const ColumnF32 c = column_f64(gc, view_geo(gc, vb.sn[s], vb.cs[s]), bvs[s], i, j, kb);
       const T* qs = q + s * vstride;
       const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
       const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);

@@ -107,6 +107,14 @@ fdk_status check_views(const fdk_geometry* g, int32_t view0, int32_t nviews) {
   return FDK_OK;
 }
 
+// Views per launch: the fewest launches of at most `cap` views, split
+// evenly (a short last launch would read and write the volume for few
+// views).
+int32_t views_per_launch(int32_t nviews, int32_t cap) {
+  const int32_t n = (nviews + cap - 1) / cap;
+  return n > 0 ? (nviews + n - 1) / n : cap;
+}
+
 // Adjoint slot rotation: the order in which each lane visits its 16 slots.
 // The tiled adjoint is bound by LDS bank conflicts among the 64 lanes of each
 // atomic add, and which rotation spreads them best depends on the view
@@ -179,7 +187,7 @@ void choose_rotation(const fdk::GeoConst& gc, const fdk::SliceRun& r, const fdk:
         const int32_t bx = static_cast<int32_t>(f[0] * (ts->nbx - 1));
         const int32_t by = static_cast<int32_t>(f[1] * (ts->nby - 1));
         const int32_t seg = static_cast<int32_t>(f[2] * (ts->nseg - 1));
-        cost += rotation_cost(gc, vb.view[s], ts->tvp, bx * fdk::kBrickX, by * fdk::kBrickY,
+        cost += rotation_cost(gc, fdk::view_geo(gc, vb.sn[s], vb.cs[s]), ts->tvp, bx * fdk::kBrickX, by * fdk::kBrickY,
                               r.k_first + seg * bz, kRotCand[c][0], kRotCand[c][1]);
       }
     }
@@ -320,9 +328,10 @@ fdk_status fdk_backproject(const fdk_geometry* g, int32_t view0, int32_t nviews,
   }
   const int64_t vstride = (int64_t)g->nu * g->nv;
   fdk::ViewBatch vb;
-  for (int32_t b = 0; b < nviews; b += fdk::kMaxViewsPerLaunch) {
-    vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
-    for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
+  const int32_t per = views_per_launch(nviews, fdk::kMaxViewsPerLaunch);
+  for (int32_t b = 0; b < nviews; b += per) {
+    vb.nviews = std::min(per, nviews - b);
+    for (int32_t s = 0; s < vb.nviews; ++s) fdk::set_view(&vb, s, g->angles[view0 + b + s]);
     const char* qb = static_cast<const char*>(q) + (size_t)b * vstride * dtype_size(q_dtype);
     for (const fdk::SliceRun& r : sl.runs) {
       const fdk::TileShape ts =
@@ -362,9 +371,10 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
       return fail(FDK_ERR_HIP, "zero fill failed: HIP error %d", e);
   }
   fdk::ViewBatch vb;
-  for (int32_t b = 0; b < nviews; b += fdk::kMaxViewsPerLaunch) {
-    vb.nviews = std::min(fdk::kMaxViewsPerLaunch, nviews - b);
-    for (int32_t s = 0; s < vb.nviews; ++s) vb.view[s] = make_view(g, g->angles[view0 + b + s]);
+  const int32_t per = views_per_launch(nviews, fdk::kFpViewsPerLaunch);
+  for (int32_t b = 0; b < nviews; b += per) {
+    vb.nviews = std::min(per, nviews - b);
+    for (int32_t s = 0; s < vb.nviews; ++s) fdk::set_view(&vb, s, g->angles[view0 + b + s]);
     for (const fdk::SliceRun& r : sl.runs) {
       // Plain runs: 32-slice bricks and a single accumulation plane; their
       // flush has no prefetch budget to respect.

@@ -8,13 +8,17 @@
 
 namespace fdk {
 
-// Views per kernel launch: the per-view constants travel in the kernel
-// argument block (48 bytes a view, within its 4 KB), and each launch reads
-// (and for the back-projector writes) the volume once and sets up each
-// brick once. Measured against 32 views a launch: the back-projector 6 %
-// faster at 2048^3, the adjoint 2 % at 2048^3 and 10 % at 256^3 from 360
-// views.
-constexpr int kMaxViewsPerLaunch = 64;
+// Views per kernel launch: each view's sine and cosine travel in the kernel
+// argument block (16 bytes a view), and each launch reads (and for the
+// back-projector writes) the volume once and sets up each brick once; the
+// views of a call are split evenly over the fewest launches. Measured at
+// 2048^3: the back-projector 6 % faster with 64 views a launch than with
+// 32, and 3 % faster again with 96. The adjoint takes at most 64: one slot
+// rotation serves all views of a launch, and with 96 views spread over the
+// circle that cost 11 % (at 64 it gains 2 % over 32 at 2048^3, 10 % at
+// 256^3 from 360 views).
+constexpr int kMaxViewsPerLaunch = 96;
+constexpr int kFpViewsPerLaunch = 64;
 
 // Per-view geometry in the reduced-cost form of Alg. 4, evaluated in FP64 on
 // the host from the view angle (Eq. 2 expanded):
@@ -33,8 +37,24 @@ struct GeoConst {
   double cu, cv, cz;  // principal point (pixels) and volume centre slice
   double ku;          // D / Du
   double kv;          // D * Dz / Dv
+  double dx, dy, d;   // voxel pitches in x and y, source to axis
+  double ox, oy;      // volume centre column (voxels)
   int32_t mirror_g;   // Nv - 1 + 2 off_v when that is an integer (Theorem 1)
 };
+
+// ViewGeo of the view with sin(beta) = s, cos(beta) = c (Eq. 2 expanded:
+// world X = Dx (i - ox), Y = -Dy (j - oy); after the rotation,
+// z = d + sin(b) X + cos(b) Y and a = cos(b) X - sin(b) Y). Host and device.
+constexpr ViewGeo view_geo(const GeoConst& gc, double s, double c) {
+  ViewGeo v{};
+  v.ci = s * gc.dx;
+  v.cj = -c * gc.dy;
+  v.c0 = gc.d - s * gc.dx * gc.ox + c * gc.dy * gc.oy;
+  v.ai = c * gc.dx;
+  v.aj = s * gc.dy;
+  v.a0 = -c * gc.dx * gc.ox - s * gc.dy * gc.oy;
+  return v;
+}
 
 // A run of global slices processed by one launch family.
 //  mirror = 0: slices k_first + t (t < n) stored at slab slice loc_lo + t.
@@ -45,7 +65,7 @@ struct SliceRun {
 };
 
 struct ViewBatch {
-  ViewGeo view[kMaxViewsPerLaunch];
+  double sn[kMaxViewsPerLaunch], cs[kMaxViewsPerLaunch];  // sin and cos of each view's angle
   int32_t nviews;
 };
 
@@ -72,8 +92,8 @@ constexpr int kPrefetchSlots = 6;       // tile entries a thread prefetches per 
 // Tiles too tall for the five-wave back-projector's slots (more than three
 // staging passes per view) go to a four-wave instance with more slots.
 constexpr int kWidePrefetchSlots = 12;
-constexpr int kTileLdsBytes = 36864;    // LDS budget for the adjoint's and the four-wave tiles
-constexpr int kBpTileLdsBytes = 29696;  // and for the five-wave back-projector's
+constexpr int kTileLdsBytes = 36352;    // LDS budget for the adjoint's and the four-wave tiles
+constexpr int kBpTileLdsBytes = 28160;  // and for the five-wave back-projector's
 constexpr int kTileEntryBytes = 16;     // (q, dq/du) of a row and of its mirror row
 
 struct TileShape {

@@ -165,7 +165,7 @@ __device__ __forceinline__ void fp_tiled_body(GeoConst gc, SliceRun run, ViewBat
                                               float* __restrict__ q, int64_t vstride,
                                               float scale, int fixed_sums) {
   extern __shared__ __attribute__((aligned(16))) int atile[];
-  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  __shared__ BrickView bvs[kFpViewsPerLaunch];
   __shared__ uint32_t hist[kMaxStageViews * kHistStride];
   __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
   __shared__ uint32_t amax_bits, amin_bits, n_nonzero, n_small, nonfinite;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void fp_tiled_body(GeoConst gc, SliceRun run, ViewBat
     amin_bits = __float_as_uint(INFINITY);
   }
   if (tid >= v_lo && tid < v_hi)
-    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
+    bvs[tid] = brick_setup(gc, view_geo(gc, vb.sn[tid], vb.cs[tid]), bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
                            MIRROR);
   const uint32_t rot = slot_rotation(ts);
   float x[kBrickZ], xm[kBrickZ];
@@ -491,12 +491,12 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
                                                              const float* __restrict__ vol,
                                                              float* __restrict__ q,
                                                              int64_t vstride, float scale) {
-  __shared__ BrickView bvs[kMaxViewsPerLaunch];
+  __shared__ BrickView bvs[kFpViewsPerLaunch];
   const int32_t tid = threadIdx.x;
   constexpr int BZ = MIRROR ? kBrickZ : kPlainBrickZ;  // slices per brick
   const BrickCoords bc = brick_coords(gc, run, ts, BZ);
   if (tid < vb.nviews)
-    bvs[tid] = brick_setup(gc, vb.view[tid], bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
+    bvs[tid] = brick_setup(gc, view_geo(gc, vb.sn[tid], vb.cs[tid]), bc.i_lo, bc.i_hi, bc.j_lo, bc.j_hi, bc.kb, 0, 0, BZ,
                            MIRROR);
   const uint32_t rot = slot_rotation(ts);
   float x[kBrickZ], xm[kBrickZ];
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
   __syncthreads();
   if (!bc.owner) return;
   for (int32_t s = 0; s < vb.nviews; ++s) {
-    const ColumnF32 c = column_f64(gc, vb.view[s], bvs[s], bc.i, bc.j, bc.kb);
+    const ColumnF32 c = column_f64(gc, view_geo(gc, vb.sn[s], vb.cs[s]), bvs[s], bc.i, bc.j, bc.kb);
     float* qs = q + s * vstride;
     const int32_t a = bvs[s].org_u + static_cast<int32_t>(c.nu);
     const int32_t nb = bvs[s].org_v + static_cast<int32_t>(c.nvb);

@@ -27,22 +27,23 @@ inline GeoConst make_geo(const fdk_geometry* g) {
   // mirrored taps line up with whole pixels only when 2 cv is an integer.
   const double G = (g->nv - 1) + 2.0 * g->off_v;
   gc.mirror_g = (std::fabs(G - std::nearbyint(G)) <= 1e-9) ? (int32_t)std::nearbyint(G) : INT32_MIN;
+  gc.dx = g->dx;
+  gc.dy = g->dy;
+  gc.d = g->sod;
+  gc.ox = 0.5 * (g->nx - 1);
+  gc.oy = 0.5 * (g->ny - 1);
   return gc;
 }
 
-// Eq. 2 expanded for one gantry angle: world X = Dx (i - cx), Y = -Dy (j - cy);
-// after the rotation, z = d + sin(b) X + cos(b) Y and a = cos(b) X - sin(b) Y.
+// Eq. 2 expanded for one gantry angle (view_geo).
 inline ViewGeo make_view(const fdk_geometry* g, double beta) {
-  const double s = std::sin(beta), c = std::cos(beta);
-  const double cx = 0.5 * (g->nx - 1), cy = 0.5 * (g->ny - 1);
-  ViewGeo v;
-  v.ci = s * g->dx;
-  v.cj = -c * g->dy;
-  v.c0 = g->sod - s * g->dx * cx + c * g->dy * cy;
-  v.ai = c * g->dx;
-  v.aj = s * g->dy;
-  v.a0 = -c * g->dx * cx - s * g->dy * cy;
-  return v;
+  return view_geo(make_geo(g), std::sin(beta), std::cos(beta));
+}
+
+// Sets view s of a launch to the gantry angle beta.
+inline void set_view(ViewBatch* vb, int32_t s, double beta) {
+  vb->sn[s] = std::sin(beta);
+  vb->cs[s] = std::cos(beta);
 }
 
 }  // namespace fdk

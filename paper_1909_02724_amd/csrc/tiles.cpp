@@ -31,8 +31,7 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
   const double kmax = gc.cz + bz;
   double wu = 0.0, wv = 0.0;
   for (int32_t s = 0; s < vb.nviews; ++s) {
-    // |sin| and |cos| of the view from its geometry: ci = sin Dx, cj = -cos Dy.
-    const double as = std::fabs(vb.view[s].ci) / g->dx, ac = std::fabs(vb.view[s].cj) / g->dy;
+    const double as = std::fabs(vb.sn[s]), ac = std::fabs(vb.cs[s]);
     const double dui = gc.ku * g->dx * (ac + as * rho) / zmin;
     const double duj = gc.ku * g->dy * (as + ac * rho) / zmin;
     wu = std::fmax(wu, (kBrickX - 1) * dui + (kBrickY - 1) * duj);

@@ -60,7 +60,7 @@ def launch_groups(chunks: Sequence[int], chunk: int, batch: int, n_all: int):
 
 def reconstruct_slab(geom, angles, produce: Producer, *, z0: int = 0,
                      nz_local: int | None = None, slab: str = "contiguous", chunk: int = 16,
-                     batch: int = 64, dtype: torch.dtype = torch.float16,
+                     batch: int = 96, dtype: torch.dtype = torch.float16,
                      kind: str = "shepp-logan", scale: float = 1.0,
                      chunks: Sequence[int] | None = None, out: torch.Tensor | None = None,
                      device="cuda", timing: SlabTiming | None = None) -> torch.Tensor:

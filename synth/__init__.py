@@ -68,13 +68,13 @@ def _cube(n: int, nuv: int, nz: int | None = None) -> Geom:
 CONFIGS = {
     # 64^3, 64 views, 64^2 detector: the small full-FDK case.
     "fdk64": dict(geom=_cube(64, 64), np=64, n_ell=8, seed=101, filter="ramlak",
-                  dtype="f32", B=64),
+                  dtype="f32", B=96),
     # 512^3, 512 views, 512^2 detector, Shepp-Logan filtered.
     "bp512": dict(geom=_cube(512, 512), np=512, n_ell=32, seed=102, filter="shepp-logan",
-                  dtype="f32", B=64),
-    # 2048^3 (32 GiB FP32 volume), 2048 views of 2048^2, launches of 64 views.
+                  dtype="f32", B=96),
+    # 2048^3 (32 GiB FP32 volume), 2048 views of 2048^2, launches of up to 96 views.
     "bp2048": dict(geom=_cube(2048, 2048), np=2048, n_ell=32, seed=103, filter="shepp-logan",
-                   dtype="f32", B=64),
+                   dtype="f32", B=96),
     # One GPU's slab of the 4096^3 problem: 4096 x 4096 x 256, the outermost
     # mirror pair of 128-slice slabs, 4096 views of 4096^2 in FP16, 16-view chunks.
     "slab4096": dict(geom=_cube(4096, 4096), np=4096, n_ell=64, seed=104, filter="shepp-logan",
@@ -83,7 +83,7 @@ CONFIGS = {
     # Differentiable: batch of 4 volumes of 256^3, 360 views of 384^2; the
     # whole volume lies inside the field of view (192 px >= 181 half-diagonal).
     "diff256": dict(geom=Geom(nx=256, ny=256, nz=256, nu=384, nv=384, sod=2000.0, sdd=4000.0),
-                    np=360, batch=4, seed=105, dtype="f32", B=64),
+                    np=360, batch=4, seed=105, dtype="f32", B=96),
 }
 
 

@@ -1,6 +1,6 @@
 """Full-size GPU parity: the 512^3 and 2048^3 workloads in the launch
-configuration the benchmark times (all views in one call, 64 views per
-launch), checked against the FP64 oracle on sampled voxels.
+configuration the benchmark times (all views in one call, split evenly
+into launches of at most 96 views), checked against the FP64 oracle on sampled voxels.
 
 512^3: the oracle makes the inputs itself (analytic phantom projections and
 its own filter), the GPU back-projects the same FP32 values.

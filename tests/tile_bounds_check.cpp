@@ -63,7 +63,7 @@ void check_run(const fdk_geometry& g, const fdk::GeoConst& gc, const fdk::SliceR
           const int32_t i_lo = bx * kBrickX, j_lo = by * kBrickY;
           const int32_t i_hi = std::min(i_lo + kBrickX - 1, gc.nx - 1);
           const int32_t j_hi = std::min(j_lo + kBrickY - 1, gc.ny - 1);
-          const BrickView b = brick_setup(gc, vb.view[s], i_lo, i_hi, j_lo, j_hi, kb, ts.tu,
+          const BrickView b = brick_setup(gc, fdk::view_geo(gc, vb.sn[s], vb.cs[s]), i_lo, i_hi, j_lo, j_hi, kb, ts.tu,
                                           ts.tv, bz, mirror);
           // Every thread of the workgroup computes a column, owners and the
           // clamped non-owners alike, so all 256 are checked.
@@ -144,7 +144,7 @@ int main(int argc, char** argv) {
     const fdk::GeoConst gc = fdk::make_geo(&g);
     fdk::ViewBatch vb{};
     vb.nviews = nviews;
-    for (int s = 0; s < nviews; ++s) vb.view[s] = fdk::make_view(&g, ang[s]);
+    for (int s = 0; s < nviews; ++s) fdk::set_view(&vb, s, ang[s]);
     // The runs the front end makes for the whole volume: mirrored pairs of
     // the lower half when the mirror is pixel-aligned (plus an odd middle
     // slice), else one plain run; and a plain run over every slice.
