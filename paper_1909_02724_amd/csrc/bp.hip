@@ -378,9 +378,9 @@ __device__ __forceinline__ void bp_brick_body(const GeoConst& gc, const SliceRun
 }
 
 // The tiled variants run five 256-thread workgroups per CU (five waves per
-// SIMD): tiles within 29 KB, 102 VGPRs. Tiles that need more staging passes
+// SIMD): tiles within 27.5 KB, 102 VGPRs. Tiles that need more staging passes
 // per view than their prefetch slots allow run the WIDE instances: four
-// workgroups per CU, 36 KB, 128 VGPRs and kWidePrefetchSlots slots.
+// workgroups per CU, 35.5 KB, 128 VGPRs and kWidePrefetchSlots slots.
 template <typename T>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 5)))
 void bp_tiled_mirror_kernel(GeoConst gc, SliceRun run, ViewBatch vb, TileShape ts,

@@ -20,8 +20,9 @@ namespace fdk {
 constexpr int kMaxViewsPerLaunch = 96;
 constexpr int kFpViewsPerLaunch = 64;
 
-// Per-view geometry in the reduced-cost form of Alg. 4, evaluated in FP64 on
-// the host from the view angle (Eq. 2 expanded):
+// Per-view geometry in the reduced-cost form of Alg. 4, evaluated in FP64
+// from the sine and cosine of the view angle (Eq. 2 expanded; view_geo, on
+// the host and in the kernels):
 //   z(i, j)   = ci*i + cj*j + c0                      (Eq. 3, Theorem 3)
 //   a(i, j)   = ai*i + aj*j + a0   gantry coordinate across the detector
 //   u         = cu + ku * a / z                        (Theorem 2)
@@ -81,11 +82,11 @@ constexpr int kBrickThreads = kBrickX * kBrickY;
 constexpr int kWaveLanes = 64;
 // Occupancy decides the back-projector's speed more than staging depth
 // does (measured on MI355X): five 256-thread workgroups per CU, hence at
-// most 29 KB of tiles (with the 3 KB of per-view constants, 32 KB a
-// workgroup) and 102 VGPRs, with two views per stage, run 5 %
+// most 27.5 KB of tiles (with the 4.5 KB of per-view brick constants, 32 KB
+// a workgroup) and 102 VGPRs, with two views per stage, run 5 %
 // faster than four with three views (and four with three 11 % (FP32) to
 // 47 % (FP16) faster than three with four). The adjoint stages up to three
-// views in 36 KB.
+// views in 35.5 KB.
 constexpr int kMaxStageViews = 3;
 constexpr int kBpStageViews = 2;
 constexpr int kPrefetchSlots = 6;       // tile entries a thread prefetches per stage

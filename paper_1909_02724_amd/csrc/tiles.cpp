@@ -68,9 +68,9 @@ TileShape tile_shape(const fdk_geometry* g, const GeoConst& gc, const SliceRun& 
     ts.vc = static_cast<int32_t>(std::max<int64_t>(vc, 0));
     return ts;
   }
-  // Back-projector: the five-wave kernel (slots prefetch slots, 29 KB of
+  // Back-projector: the five-wave kernel (slots prefetch slots, 27.5 KB of
   // tiles) when it stages all kBpStageViews views per stage, else the
-  // four-wave one (more slots and 36 KB) if that stages more.
+  // four-wave one (more slots and 35.5 KB) if that stages more.
   const int64_t vc5 = std::min<int64_t>({kBpStageViews, kBpTileLdsBytes / per_view, slots / ts.rows});
   const int64_t wide_slots = static_cast<int64_t>(slots) * kWidePrefetchSlots / kPrefetchSlots;
   const int64_t vc4 = std::min<int64_t>({kBpStageViews, kTileLdsBytes / per_view, wide_slots / ts.rows});
