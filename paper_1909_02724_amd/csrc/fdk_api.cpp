@@ -115,6 +115,19 @@ int32_t views_per_launch(int32_t nviews, int32_t cap) {
   return n > 0 ? (nviews + n - 1) / n : cap;
 }
 
+// Views per launch of the adjoint: up to kMaxViewsPerLaunch when every
+// launch's views then span at most kFpWideSpanRad of angle, else up to
+// kFpViewsPerLaunch.
+int32_t adjoint_views_per_launch(const double* angles, int32_t nviews) {
+  const int32_t wide = views_per_launch(nviews, fdk::kMaxViewsPerLaunch);
+  for (int32_t b = 0; b < nviews; b += wide) {
+    const int32_t n = std::min(wide, nviews - b);
+    const auto [lo, hi] = std::minmax_element(angles + b, angles + b + n);
+    if (*hi - *lo > fdk::kFpWideSpanRad) return views_per_launch(nviews, fdk::kFpViewsPerLaunch);
+  }
+  return wide;
+}
+
 // Adjoint slot rotation: the order in which each lane visits its 16 slots.
 // The tiled adjoint is bound by LDS bank conflicts among the 64 lanes of each
 // atomic add, and which rotation spreads them best depends on the view
@@ -371,7 +384,7 @@ fdk_status fdk_forward_project(const fdk_geometry* g, int32_t view0, int32_t nvi
       return fail(FDK_ERR_HIP, "zero fill failed: HIP error %d", e);
   }
   fdk::ViewBatch vb;
-  const int32_t per = views_per_launch(nviews, fdk::kFpViewsPerLaunch);
+  const int32_t per = adjoint_views_per_launch(g->angles + view0, nviews);
   for (int32_t b = 0; b < nviews; b += per) {
     vb.nviews = std::min(per, nviews - b);
     for (int32_t s = 0; s < vb.nviews; ++s) fdk::set_view(&vb, s, g->angles[view0 + b + s]);

@@ -13,12 +13,15 @@ namespace fdk {
 // back-projector writes) the volume once and sets up each brick once; the
 // views of a call are split evenly over the fewest launches. Measured at
 // 2048^3: the back-projector 6 % faster with 64 views a launch than with
-// 32, and 3 % faster again with 96. The adjoint takes at most 64: one slot
-// rotation serves all views of a launch, and with 96 views spread over the
-// circle that cost 11 % (at 64 it gains 2 % over 32 at 2048^3, 10 % at
-// 256^3 from 360 views).
+// 32, and 3 % faster again with 96. The adjoint takes 96 only when every
+// launch's views then span at most kFpWideSpanRad: one slot rotation serves
+// all views of a launch, and 96 views spread over 120 degrees cost it 11 %
+// at 2048^3, while launches over 68 and 90 degrees gained 3 % (512^3 from
+// 512 views, 256^3 from 360). Otherwise it takes at most 64 (2 % faster than
+// 32 at 2048^3, 10 % at 256^3 from 360 views).
 constexpr int kMaxViewsPerLaunch = 96;
 constexpr int kFpViewsPerLaunch = 64;
+constexpr double kFpWideSpanRad = 1.75;  // about 100 degrees
 
 // Per-view geometry in the reduced-cost form of Alg. 4, evaluated in FP64
 // from the sine and cosine of the view angle (Eq. 2 expanded; view_geo, on

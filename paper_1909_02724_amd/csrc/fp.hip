@@ -165,7 +165,7 @@ __device__ __forceinline__ void fp_tiled_body(GeoConst gc, SliceRun run, ViewBat
                                               float* __restrict__ q, int64_t vstride,
                                               float scale, int fixed_sums) {
   extern __shared__ __attribute__((aligned(16))) int atile[];
-  __shared__ BrickView bvs[kFpViewsPerLaunch];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
   __shared__ uint32_t hist[kMaxStageViews * kHistStride];
   __shared__ uint32_t kcount[kMaxStageViews], mbits[kMaxStageViews];
   __shared__ uint32_t amax_bits, amin_bits, n_nonzero, n_small, nonfinite;
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kThreads) void fp_direct_kernel(GeoConst gc, SliceR
                                                              const float* __restrict__ vol,
                                                              float* __restrict__ q,
                                                              int64_t vstride, float scale) {
-  __shared__ BrickView bvs[kFpViewsPerLaunch];
+  __shared__ BrickView bvs[kMaxViewsPerLaunch];
   const int32_t tid = threadIdx.x;
   constexpr int BZ = MIRROR ? kBrickZ : kPlainBrickZ;  // slices per brick
   const BrickCoords bc = brick_coords(gc, run, ts, BZ);
